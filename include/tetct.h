@@ -1,0 +1,204 @@
+/*
+ * tetct: tetrahedral-mesh cone-beam CT projector for AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the linear CT model A x = b of Biguri et al.,
+ * "Numerically robust tetrahedron-based tomographic forward and backward
+ * projectors on parallel architectures" (Section II-A, Eq. 1): the entry
+ * a_ij of A is the length of ray j inside tetrahedron i, x holds one
+ * attenuation value per tetrahedron and b one value per detector pixel and
+ * angle.  A is never stored; each call recomputes a_ij by walking every ray
+ * through the mesh (Section II-A, matrix-free operator; Section II-D,
+ * Algorithm 2).
+ *
+ * Conventions shared by every call
+ *   - Plain C99.  All functions return tct_status (0 = success) unless noted.
+ *     On error, tct_last_error() gives a message (thread-local, valid until the
+ *     next call on the same thread).  No exceptions cross this interface and
+ *     nothing calls exit().
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the device the handle was created for.  Device arrays
+ *     are caller-owned unless stated: the library never frees them.
+ *   - float is IEEE-754 binary32, double binary64, ids are int32 (-1 = none).
+ *   - Face k of a tetrahedron is the face opposite its vertex k; neighbour k
+ *     is the tetrahedron across face k (the paper's element graph, Section
+ *     II-B, Fig. 1: nD+1 nodes and nD+1 ordered neighbours per element).
+ *   - tct_stream is a hipStream_t (NULL = the default stream).  Compute calls
+ *     are asynchronous on that stream; argument errors are reported
+ *     synchronously before anything is enqueued.
+ *   - Tetrahedron-indexed device arrays (x, xhat) use the library's
+ *     *internal* order (a spatial reordering made at mesh creation).
+ *     tct_mesh_to_internal / tct_mesh_to_user convert; tct_mesh_permutation
+ *     exports the map.
+ *   - Rays: ray id r = (a * nv + j) * nu + i for angle a, detector row j and
+ *     column i; projections are laid out proj[a][j][i] (float, i fastest).
+ *     Ray r runs from the source point S to the pixel centre P (Algorithm 2's
+ *     R1, R2).  a_ij is computed for t in [0, 1] along S + t (P - S); the
+ *     whole mesh must lie strictly between the source and the detector plane
+ *     (checked: TCT_E_GEOM).  Rays that miss the mesh give 0.
+ *   - Ties (rays through vertices, along edges, inside face planes) are
+ *     resolved as the limit of the ray translated by eps*U + eps^2*V,
+ *     eps -> 0+, U and V the detector axes of the ray's angle: every ray then
+ *     has one well-defined sequence of visited tetrahedra, zero-length
+ *     passages included (Fig. 3), and lengths that add up to its chord.
+ */
+#ifndef TETCT_H
+#define TETCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* tct_stream; /* hipStream_t */
+typedef struct tct_mesh tct_mesh;
+typedef struct tct_geom tct_geom;
+typedef struct tct_batch tct_batch;
+
+typedef enum {
+  TCT_OK = 0,
+  TCT_E_ARG = -1,              /* bad argument (null pointer, size, id out of range) */
+  TCT_E_MESH_DEGENERATE = -2,  /* a tetrahedron has zero volume */
+  TCT_E_MESH_NONMANIFOLD = -3, /* a face shared by >2 tetrahedra, or an open/inconsistent boundary */
+  TCT_E_MESH_NONCONVEX = -4,   /* the hull is not convex (the method requires it, Section II-D) */
+  TCT_E_MESH_DISCONNECTED = -5,/* the boundary surface has more than one component */
+  TCT_E_GEOM = -6,             /* the mesh is not strictly between source and detector */
+  TCT_E_NOMEM = -7,            /* device or host allocation failed */
+  TCT_E_HIP = -8,              /* a HIP runtime call failed */
+  TCT_E_WALK = -9,             /* device walk failures were counted (see tct_stats) */
+  TCT_E_CAPACITY = -10         /* an output buffer is too small (required size reported) */
+} tct_status;
+
+/* Circular cone-beam geometry (the paper's experiments, Section III-A: cone
+ * beam, circular trajectory, equidistant angles).  Rotation is about +z.  For
+ * angle theta: source S = dso (cos, sin, 0); detector centre
+ * D = -(dsd - dso) (cos, sin, 0); U = (-sin, cos, 0); V = (0, 0, 1).  Pixel
+ * centres: u_i = (i - (nu-1)/2) du + off_u, v_j = (j - (nv-1)/2) dv + off_v,
+ * P = D + u_i U + v_j V.  cos/sin are evaluated in double and replaced by the
+ * exact 0/+-1 within 1e-12 of a quarter turn; every vector is then rounded to
+ * float, and P is formed in float as fl(fl(D + fl(u U)) + fl(v V)) without
+ * fused multiply-add. */
+typedef struct {
+  double dso, dsd;
+  int32_t nu, nv;
+  double du, dv, off_u, off_v;
+} tct_cone;
+
+/* Device-side counters accumulated by every walk on a mesh since the last
+ * reset.  segments counts visited tetrahedra (zero-length passages
+ * included); fp64_stage counts sign tests the float32 filter could not
+ * certify; exact_stage those the float64 filter could not certify either;
+ * perturbed_ties those decided by the eps*U / eps^2*V terms; failed counts
+ * rays that stopped without leaving the mesh (should stay 0). */
+typedef struct {
+  int64_t rays, segments, zero_len, fp64_stage, exact_stage, perturbed_ties, failed, reserved;
+} tct_stats;
+
+/* ---------------------------------------------------------------- mesh */
+
+/* Flags for tct_mesh_create. */
+#define TCT_MESH_NO_REORDER 1u /* keep the user's tetrahedron order as the internal order */
+#define TCT_MESH_HOST_ONLY 2u  /* build and validate on the host only; no device upload (compute calls fail) */
+
+/* Build a mesh from nodes and elements (Section II-B).
+ *   verts  host float [nv][3]  node coordinates
+ *   tets   host int32 [nt][4]  node ids of each tetrahedron, any orientation
+ *   nbrs   host int32 [nt][4]  neighbour across face k, -1 on the boundary, or
+ *                              NULL to compute them; when given they are checked
+ *   device HIP device ordinal
+ * Inputs are copied; the caller may free them on return.  Validation:
+ * ids in range, non-zero volume (exact), each face shared by at most two
+ * tetrahedra, a closed, connected, convex boundary (exact tests at every
+ * boundary edge).  Tetrahedra are reordered along a Morton curve of their
+ * centroids unless TCT_MESH_NO_REORDER.  Builds the boundary-face list
+ * (Section II-B) and a bounding-volume hierarchy over it (entry search,
+ * Section II-E).  On error *out is set to NULL. */
+tct_status tct_mesh_create(const float* verts, int32_t nv, const int32_t* tets, int32_t nt, const int32_t* nbrs,
+                           uint32_t flags, int device, tct_mesh** out);
+
+/* Sizes: node count, tetrahedron count, boundary faces, device bytes held. Any pointer may be NULL. */
+tct_status tct_mesh_counts(const tct_mesh* m, int32_t* nv, int32_t* nt, int32_t* nboundary, int64_t* device_bytes);
+
+/* host int32 [nt]: user id of each internal tetrahedron. */
+tct_status tct_mesh_permutation(const tct_mesh* m, int32_t* internal_to_user);
+
+/* host int32 [nt][4]: neighbour (user ids, -1 boundary) across face k of each
+ * user tetrahedron, with faces numbered by the user's vertex order. */
+tct_status tct_mesh_neighbors(const tct_mesh* m, int32_t* nbrs);
+
+/* device float [nt]: x_internal[i] = x_user[perm[i]]  /  x_user[perm[i]] = x_internal[i]. */
+tct_status tct_mesh_to_internal(const tct_mesh* m, const float* x_user, float* x_internal, tct_stream s);
+tct_status tct_mesh_to_user(const tct_mesh* m, const float* x_internal, float* x_user, tct_stream s);
+
+/* Counters since the last reset; synchronises the device.  Returns TCT_E_WALK
+ * when failed > 0 (the counters are still written). */
+tct_status tct_stats_read(const tct_mesh* m, tct_stats* out, int reset);
+
+void tct_mesh_destroy(tct_mesh* m);
+
+/* ---------------------------------------------------------------- geometry */
+
+/* angles_rad host double [na].  Copies to the device. */
+tct_status tct_geom_create(const tct_cone* cone, const double* angles_rad, int32_t na, int device, tct_geom** out);
+
+/* Number of rays na * nv * nu. */
+int64_t tct_geom_nrays(const tct_geom* g);
+
+/* host float: S, D, U, V [na][3] and the pixel-centre tables u [nu], v [nv], as used by the kernels. */
+tct_status tct_geom_frame(const tct_geom* g, float* S, float* D, float* U, float* V, float* u, float* v);
+
+void tct_geom_destroy(tct_geom* g);
+
+/* ---------------------------------------------------------------- operators */
+
+/* Entry faces (Section II-E: the boundary element each ray enters by).
+ * entry: device int32 [nrays], boundary-face index or -1 for a miss.  The
+ * array can be passed to the operators below to skip the search (it depends
+ * only on the mesh and the geometry). */
+tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s);
+
+/* Forward projection b_j = sum_i a_ij x_i (Eq. 2).
+ *   x     device float [nt], internal order
+ *   proj  device float [na][nv][nu], overwritten
+ *   entry device int32 [nrays] from tct_entry, or NULL to search in-kernel */
+tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
+                       tct_stream s);
+
+#define TCT_BP_ATOMIC 0 /* float32 atomic scatter along each ray (Section II-F) */
+#define TCT_BP_GATHER 1 /* deterministic: per-tetrahedron lists of (ray, length), summed in ray order */
+
+/* Backprojection xhat_i = sum_j a_ij y_j (Eq. 3 with the detector index on y).
+ *   proj  device float [na][nv][nu]
+ *   xhat  device float [nt], internal order; overwritten unless accumulate != 0
+ *   mode  TCT_BP_ATOMIC or TCT_BP_GATHER.  GATHER gives bitwise-identical results
+ *         run to run; it allocates stream-ordered scratch and synchronises the
+ *         stream once per angle chunk. */
+tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
+                           int accumulate, const int32_t* entry, tct_stream s);
+
+/* Visited tetrahedra of selected rays, zero-length passages included, in CSR form.
+ *   ray_ids  device int64 [nrays]
+ *   offsets  device int64 [nrays + 1]   written: ray k owns [offsets[k], offsets[k+1])
+ *   tets     device int32 [cap]          user ids
+ *   lengths  device float [cap]
+ * Synchronises the stream.  If the total exceeds cap, returns TCT_E_CAPACITY
+ * with offsets filled and *needed set. */
+tct_status tct_trace(const tct_mesh* m, const tct_geom* g, const int64_t* ray_ids, int32_t nrays, int64_t* offsets,
+                     int32_t* tets, float* lengths, int64_t cap, int64_t* needed, tct_stream s);
+
+/* Same for caller-given rays: device float [n][3] arrays S, P (endpoints) and
+ * U, V (tie-breaking axes; {P - S, U, V} must be a basis, else the ray is
+ * counted as failed and gets an empty path). */
+tct_status tct_trace_rays(const tct_mesh* m, const float* S, const float* P, const float* U, const float* V,
+                          int32_t n, int64_t* offsets, int32_t* tets, float* lengths, int64_t cap, int64_t* needed,
+                          tct_stream s);
+
+/* ---------------------------------------------------------------- misc */
+
+const char* tct_last_error(void);
+const char* tct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TETCT_H */

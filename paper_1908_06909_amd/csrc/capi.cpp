@@ -1,0 +1,332 @@
+// The C interface declared in include/tetct.h.
+#include <algorithm>
+#include <cstring>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tct {
+extern thread_local std::string g_err;
+
+namespace {
+
+// Makes the handle's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+tct_status need_device(const tct_mesh* m) {
+  if (!m) {
+    set_error("null mesh");
+    return TCT_E_ARG;
+  }
+  if (m->host_only) {
+    set_error("mesh was created with TCT_MESH_HOST_ONLY");
+    return TCT_E_ARG;
+  }
+  return TCT_OK;
+}
+
+tct_status check_pair(const tct_mesh* m, const tct_geom* g) {
+  tct_status st = need_device(m);
+  if (st != TCT_OK) return st;
+  if (!g) {
+    set_error("null geometry");
+    return TCT_E_ARG;
+  }
+  if (g->device != m->device) {
+    set_error("mesh and geometry live on different devices");
+    return TCT_E_ARG;
+  }
+  return check_geometry(m, g);
+}
+
+}  // namespace
+
+int default_tile_u() { return 8; }
+
+}  // namespace tct
+
+using namespace tct;
+
+extern "C" {
+
+const char* tct_last_error(void) { return g_err.c_str(); }
+
+const char* tct_version(void) { return "tetct 0.1 gfx950"; }
+
+tct_status tct_mesh_create(const float* verts, int32_t nv, const int32_t* tets, int32_t nt, const int32_t* nbrs,
+                           uint32_t flags, int device, tct_mesh** out) {
+  if (!out) {
+    set_error("tct_mesh_create: null output handle");
+    return TCT_E_ARG;
+  }
+  *out = nullptr;
+  if (flags & TCT_MESH_HOST_ONLY) return mesh_build(verts, nv, tets, nt, nbrs, flags, device, out);
+  DeviceGuard dg(device);
+  if (!dg.ok) {
+    set_error("tct_mesh_create: cannot select the device");
+    return TCT_E_HIP;
+  }
+  return mesh_build(verts, nv, tets, nt, nbrs, flags, device, out);
+}
+
+tct_status tct_mesh_counts(const tct_mesh* m, int32_t* nv, int32_t* nt, int32_t* nboundary, int64_t* device_bytes) {
+  if (!m) {
+    set_error("null mesh");
+    return TCT_E_ARG;
+  }
+  if (nv) *nv = m->nv;
+  if (nt) *nt = m->nt;
+  if (nboundary) *nboundary = m->nb;
+  if (device_bytes) *device_bytes = m->device_bytes;
+  return TCT_OK;
+}
+
+tct_status tct_mesh_permutation(const tct_mesh* m, int32_t* internal_to_user) {
+  if (!m || !internal_to_user) {
+    set_error("null argument");
+    return TCT_E_ARG;
+  }
+  std::memcpy(internal_to_user, m->perm.data(), sizeof(int32_t) * m->perm.size());
+  return TCT_OK;
+}
+
+tct_status tct_mesh_neighbors(const tct_mesh* m, int32_t* nbrs) {
+  if (!m || !nbrs) {
+    set_error("null argument");
+    return TCT_E_ARG;
+  }
+  std::memcpy(nbrs, m->user_nbrs.data(), sizeof(int32_t) * m->user_nbrs.size());
+  return TCT_OK;
+}
+
+tct_status tct_mesh_to_internal(const tct_mesh* m, const float* x_user, float* x_internal, tct_stream s) {
+  tct_status st = need_device(m);
+  if (st != TCT_OK) return st;
+  if (!x_user || !x_internal || x_user == x_internal) {
+    set_error("tct_mesh_to_internal: null or aliased arrays");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return launch_permute(x_user, x_internal, m->d_perm, m->nt, 0, (hipStream_t)s);
+}
+
+tct_status tct_mesh_to_user(const tct_mesh* m, const float* x_internal, float* x_user, tct_stream s) {
+  tct_status st = need_device(m);
+  if (st != TCT_OK) return st;
+  if (!x_user || !x_internal || x_user == x_internal) {
+    set_error("tct_mesh_to_user: null or aliased arrays");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return launch_permute(x_internal, x_user, m->d_perm, m->nt, 1, (hipStream_t)s);
+}
+
+tct_status tct_stats_read(const tct_mesh* m, tct_stats* out, int reset) {
+  tct_status st = need_device(m);
+  if (st != TCT_OK) return st;
+  if (!out) {
+    set_error("null stats output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  unsigned long long h[kNumCounters];
+  TCT_HIP(hipDeviceSynchronize());
+  TCT_HIP(hipMemcpy(h, m->d_counters, sizeof(h), hipMemcpyDeviceToHost));
+  out->rays = (int64_t)h[kRays];
+  out->segments = (int64_t)h[kSegments];
+  out->zero_len = (int64_t)h[kZeroLen];
+  out->fp64_stage = (int64_t)h[kFp64Stage];
+  out->exact_stage = (int64_t)h[kExactStage];
+  out->perturbed_ties = (int64_t)h[kPerturbed];
+  out->failed = (int64_t)h[kFailed];
+  out->reserved = 0;
+  if (reset) {
+    unsigned long long z[kNumCounters] = {0};
+    TCT_HIP(hipMemcpy(m->d_counters, z, sizeof(z), hipMemcpyHostToDevice));
+  }
+  if (out->failed > 0) {
+    set_error("walk failures were counted");
+    return TCT_E_WALK;
+  }
+  return TCT_OK;
+}
+
+void tct_mesh_destroy(tct_mesh* m) {
+  if (!m) return;
+  if (!m->host_only) {
+    DeviceGuard dg(m->device);
+    mesh_free_device(m);
+  }
+  delete m;
+}
+
+tct_status tct_geom_create(const tct_cone* cone, const double* angles_rad, int32_t na, int device, tct_geom** out) {
+  if (!out) {
+    set_error("tct_geom_create: null output handle");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(device);
+  if (!dg.ok) {
+    set_error("tct_geom_create: cannot select the device");
+    return TCT_E_HIP;
+  }
+  return geom_build(cone, angles_rad, na, device, out);
+}
+
+int64_t tct_geom_nrays(const tct_geom* g) { return g ? g->nrays() : 0; }
+
+tct_status tct_geom_frame(const tct_geom* g, float* S, float* D, float* U, float* V, float* u, float* v) {
+  if (!g) {
+    set_error("null geometry");
+    return TCT_E_ARG;
+  }
+  for (int a = 0; a < g->na; ++a)
+    for (int k = 0; k < 3; ++k) {
+      const float* f = &g->frame[12 * (size_t)a];
+      if (S) S[3 * a + k] = f[k];
+      if (D) D[3 * a + k] = f[3 + k];
+      if (U) U[3 * a + k] = f[6 + k];
+      if (V) V[3 * a + k] = f[9 + k];
+    }
+  if (u) std::memcpy(u, g->ut.data(), 4 * g->ut.size());
+  if (v) std::memcpy(v, g->vt.data(), 4 * g->vt.size());
+  return TCT_OK;
+}
+
+void tct_geom_destroy(tct_geom* g) {
+  if (!g) return;
+  DeviceGuard dg(g->device);
+  if (g->d_frame) (void)hipFree(g->d_frame);
+  if (g->d_ut) (void)hipFree(g->d_ut);
+  if (g->d_vt) (void)hipFree(g->d_vt);
+  delete g;
+}
+
+tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!entry) {
+    set_error("tct_entry: null output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return launch_pixel_walk(kModeEntry, m, g, 0, g->na, nullptr, nullptr, nullptr, entry, nullptr, nullptr, nullptr,
+                           nullptr, default_tile_u(), (hipStream_t)s);
+}
+
+tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
+                       tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!x || !proj) {
+    set_error("tct_forward: null input or output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return launch_pixel_walk(kModeForward, m, g, 0, g->na, entry, x, proj, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           default_tile_u(), (hipStream_t)s);
+}
+
+tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
+                           int accumulate, const int32_t* entry, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!proj || !xhat) {
+    set_error("tct_backproject: null input or output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  if (mode == TCT_BP_GATHER)
+    return backproject_gather(m, g, proj, xhat, accumulate, entry, default_tile_u(), (hipStream_t)s);
+  if (mode != TCT_BP_ATOMIC) {
+    set_error("tct_backproject: unknown mode");
+    return TCT_E_ARG;
+  }
+  if (!accumulate) {
+    st = launch_fill(xhat, m->nt, 0.f, (hipStream_t)s);
+    if (st != TCT_OK) return st;
+  }
+  return launch_pixel_walk(kModeBackAtomic, m, g, 0, g->na, entry, proj, xhat, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, default_tile_u(), (hipStream_t)s);
+}
+
+namespace {
+tct_status trace_common(const tct_mesh* m, const tct_geom* g, const int64_t* ids, const float* S, const float* P,
+                        const float* U, const float* V, int32_t n, int64_t* offsets, int32_t* tets, float* lens,
+                        int64_t cap, int64_t* needed, hipStream_t s) {
+  if (n < 0 || !offsets || (cap > 0 && (!tets || !lens))) {
+    set_error("tct_trace: bad arguments");
+    return TCT_E_ARG;
+  }
+  if (n == 0) {
+    int64_t z = 0;
+    TCT_HIP(hipMemcpyAsync(offsets, &z, 8, hipMemcpyHostToDevice, s));
+    TCT_HIP(hipStreamSynchronize(s));
+    if (needed) *needed = 0;
+    return TCT_OK;
+  }
+  int64_t* counts = nullptr;
+  TCT_HIP(hipMallocAsync((void**)&counts, sizeof(int64_t) * (size_t)n, s));
+  tct_status st = launch_list_walk(kModeCountAll, m, g, ids, S, P, U, V, n, counts, nullptr, nullptr, nullptr, s);
+  std::vector<int64_t> h(n), off(n + 1);
+  if (st == TCT_OK) {
+    if (hipMemcpyAsync(h.data(), counts, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = hip_fail(hipGetLastError(), "tct_trace: count copy");
+  }
+  (void)hipFreeAsync(counts, s);
+  if (st != TCT_OK) return st;
+  off[0] = 0;
+  for (int32_t i = 0; i < n; ++i) off[i + 1] = off[i] + h[i];
+  TCT_HIP(hipMemcpyAsync(offsets, off.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s));
+  if (needed) *needed = off[n];
+  if (off[n] > cap) {
+    TCT_HIP(hipStreamSynchronize(s));
+    set_error("tct_trace: output capacity too small");
+    return TCT_E_CAPACITY;
+  }
+  st = launch_list_walk(kModeTrace, m, g, ids, S, P, U, V, n, nullptr, offsets, tets, lens, s);
+  if (st != TCT_OK) return st;
+  TCT_HIP(hipStreamSynchronize(s));
+  return TCT_OK;
+}
+}  // namespace
+
+tct_status tct_trace(const tct_mesh* m, const tct_geom* g, const int64_t* ray_ids, int32_t nrays, int64_t* offsets,
+                     int32_t* tets, float* lengths, int64_t cap, int64_t* needed, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!ray_ids && nrays > 0) {
+    set_error("tct_trace: null ray ids");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return trace_common(m, g, ray_ids, nullptr, nullptr, nullptr, nullptr, nrays, offsets, tets, lengths, cap, needed,
+                      (hipStream_t)s);
+}
+
+tct_status tct_trace_rays(const tct_mesh* m, const float* S, const float* P, const float* U, const float* V,
+                          int32_t n, int64_t* offsets, int32_t* tets, float* lengths, int64_t cap, int64_t* needed,
+                          tct_stream s) {
+  tct_status st = need_device(m);
+  if (st != TCT_OK) return st;
+  if (n > 0 && (!S || !P || !U || !V)) {
+    set_error("tct_trace_rays: null ray arrays");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return trace_common(m, nullptr, nullptr, S, P, U, V, n, offsets, tets, lengths, cap, needed, (hipStream_t)s);
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal types shared by the host and device parts of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tetct.h"
+
+namespace tct {
+
+// One bounding-volume-hierarchy node over boundary faces, 32 bytes, stored
+// in depth-first preorder: an interior node's first child is the next node;
+// `skip` is the node after its whole subtree (-1 past the end).  `leaf` is
+// -1 for interior nodes, else first_face * 8 + count (count <= 7).
+struct BvhNode {
+  float lo[3];
+  int skip;
+  float hi[3];
+  int leaf;
+};
+
+// Device view of a mesh.  Each tetrahedron has its four vertex ids sorted
+// ascending (ids are only used at creation); face f is opposite its f-th
+// vertex.  faces[4 t + f] describes the tetrahedron across face f:
+//   .x  bits: (neighbour << 2) | back, where `back` is the neighbour's local
+//       index of its vertex not on the shared face; -1 on the boundary
+//   .yzw coordinates of that vertex.
+// Because both tetrahedra list their vertices in ascending id order, the
+// shared face's three vertices appear in the same relative order in both,
+// which fixes the map between the two local numberings.
+// bfaces[4 b + 0..3] describes boundary face b with its owner:
+//   [0] xyz vertex slot 0, w = owner (int bits)
+//   [1] xyz vertex slot 1, w = slot local indices (bits 0-1, 2-3, 4-5) | face << 6
+//   [2] xyz vertex slot 2
+//   [3] xyz owner's vertex opposite the face
+// with slots ordered so that (slot1 - slot0) x (slot2 - slot0) points out of the mesh.
+struct MeshView {
+  const float4* faces;
+  const float4* bfaces;
+  const BvhNode* bvh;
+  const int* perm;  // internal -> user tetrahedron id
+  int nt;
+  int nb;
+  unsigned long long* counters;  // tct_stats fields, int64 each
+};
+
+// Cone-beam frames: frame[12 a + 0..11] = S, D, U, V of angle a.
+struct GeomView {
+  const float* frame;
+  const float* ut;
+  const float* vt;
+  int na, nu, nv;
+};
+
+// Stats slots in MeshView::counters (same order as tct_stats).
+enum Counter {
+  kRays = 0,
+  kSegments,
+  kZeroLen,
+  kFp64Stage,
+  kExactStage,
+  kPerturbed,
+  kFailed,
+  kNumCounters = 8
+};
+
+void set_error(const std::string& msg);
+tct_status hip_fail(hipError_t e, const char* what);
+
+#define TCT_HIP(call)                                             \
+  do {                                                            \
+    hipError_t _e = (call);                                       \
+    if (_e != hipSuccess) return ::tct::hip_fail(_e, #call);      \
+  } while (0)
+
+}  // namespace tct
+
+// Opaque handles.
+struct tct_mesh {
+  int device = 0;
+  int nv = 0, nt = 0, nb = 0;
+  bool host_only = false;
+  std::vector<int32_t> perm;       // internal -> user
+  std::vector<int32_t> inv_perm;   // user -> internal
+  std::vector<int32_t> user_nbrs;  // [nt][4] user numbering
+  float lo[3], hi[3];              // bounding box of the nodes
+  float4* d_faces = nullptr;
+  float4* d_bfaces = nullptr;
+  tct::BvhNode* d_bvh = nullptr;
+  int32_t* d_perm = nullptr;
+  int32_t* d_inv_perm = nullptr;
+  unsigned long long* d_counters = nullptr;
+  int nbvh = 0;
+  int64_t device_bytes = 0;
+  tct::MeshView view() const {
+    tct::MeshView v;
+    v.faces = d_faces;
+    v.bfaces = d_bfaces;
+    v.bvh = d_bvh;
+    v.perm = d_perm;
+    v.nt = nt;
+    v.nb = nb;
+    v.counters = d_counters;
+    return v;
+  }
+};
+
+struct tct_geom {
+  int device = 0;
+  tct_cone cone;
+  int na = 0;
+  std::vector<double> angles;
+  std::vector<float> frame;  // [na][12]
+  std::vector<float> ut, vt;
+  float* d_frame = nullptr;
+  float* d_ut = nullptr;
+  float* d_vt = nullptr;
+  tct::GeomView view() const {
+    tct::GeomView v;
+    v.frame = d_frame;
+    v.ut = d_ut;
+    v.vt = d_vt;
+    v.na = na;
+    v.nu = cone.nu;
+    v.nv = cone.nv;
+    return v;
+  }
+  int64_t nrays() const { return (int64_t)na * cone.nu * cone.nv; }
+};

@@ -1,0 +1,44 @@
+// Kernel launchers (walk.hip, gather.hip) used by the C interface.
+#pragma once
+
+#include "common.h"
+
+namespace tct {
+
+enum WalkMode {
+  kModeEntry = 0,
+  kModeForward = 1,
+  kModeBackAtomic = 2,
+  kModeCountAll = 3,
+  kModeCountPos = 4,
+  kModeTrace = 5,
+  kModeGatherFill = 6,
+};
+
+tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
+                             const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
+                             int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
+                             hipStream_t s);
+
+tct_status launch_list_walk(int mode, const tct_mesh* m, const tct_geom* g, const int64_t* ids, const float* S,
+                            const float* P, const float* U, const float* V, int32_t n, int64_t* counts,
+                            const int64_t* offsets, int32_t* tets, float* lens, hipStream_t s);
+
+tct_status launch_fill(float* p, int64_t n, float v, hipStream_t s);
+tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s);
+
+tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
+                              const int32_t* entry, int tile_u, hipStream_t s);
+
+tct_status exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_host, hipStream_t s);
+
+// Host-side builders (mesh.cpp).
+tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32_t nt, const int32_t* nbrs,
+                      uint32_t flags, int device, tct_mesh** out);
+void mesh_free_device(tct_mesh* m);
+tct_status geom_build(const tct_cone* cone, const double* angles, int32_t na, int device, tct_geom** out);
+tct_status check_geometry(const tct_mesh* m, const tct_geom* g);
+
+int default_tile_u();
+
+}  // namespace tct

@@ -1,0 +1,565 @@
+// Ray walk kernels for gfx950.
+//
+// One lane per detector ray (Algorithm 2 launches one thread per pixel); a
+// wavefront covers a tile of tile_u x tile_v = 64 pixels of one angle, so
+// neighbouring rays, which cross nearby tetrahedra, share a wave and its
+// cache lines (the paper found small square pixel blocks fastest, Section
+// II-F).
+//
+// Per ray: find the boundary face it enters by (a BVH over boundary faces
+// replaces the paper's R*-tree, Section II-E), then step from tetrahedron to
+// neighbour.  The state carried from step to step is the face the ray came
+// in by, as three vertex slots (a0, a1, a2) ordered so that all three edge
+// signs sigma(a0,a1), sigma(a1,a2), sigma(a2,a0) are -1 (the ray enters
+// through it), plus the current tetrahedron's fourth vertex v.  With
+// s_k = sigma(v, a_k), the ray leaves
+//   through the face opposite a2 iff s0 = -1 and s1 = +1,
+//   through the face opposite a0 iff s1 = -1 and s2 = +1,
+//   through the face opposite a1 iff s2 = -1 and s0 = +1,
+// and the next entry face is the current one with slot k replaced by v.  One
+// 16-byte record per (tetrahedron, face) gives the neighbour, its local index
+// of the vertex opposite the shared face, and that vertex's coordinates, so a
+// step costs one dependent load (plus x for the forward projection).
+//
+// sigma(p, q) is the exact sign of det[P - S, p - S, q - S] for the ray
+// S -> P translated by eps U + eps^2 V (eps -> 0+), which makes the walk
+// well defined through vertices, edges and face planes (the failure cases of
+// Section II-C, Fig. 3) without the paper's escalating epsilon.  It is first
+// estimated in float32 as (q - p) . ((P - S) x (p - S)) with a certified
+// error bound; the rare uncertain cases go to a non-inlined float64 /
+// exact-expansion routine (exact.h).
+#include "common.h"
+#include "exact.h"
+#include "kernels.h"
+
+namespace tct {
+
+namespace {
+
+// Float32 filter constants: every monomial of (q-p).((P-S)x(p-S)) carries at
+// most 8 roundings (three input differences, product and difference in the
+// cross product, the outer product, two additions); with the bound itself
+// evaluated in float32 from rounded magnitudes, 10 * 2^-24 * perm covers
+// gamma_8 * perm of the exact inputs.  The absolute term covers underflow.
+constexpr float kFilterRel = 10.0f * 5.9604644775390625e-8f;
+constexpr float kFilterAbs = 7.888609052210118e-31f;  // 2^-100
+
+struct Ray {
+  float3 S, P, U, V;
+  float3 d;   // fl(P - S)
+  float3 ad;  // |d|
+  float3 M;   // fl(S + d / 2): reference point near the mesh for ray parameters
+  float dn;   // |d| (Euclidean)
+};
+
+struct LaneStats {
+  int steps = 0, zero = 0, fp64 = 0, exact = 0, pert = 0, failed = 0;
+};
+
+__device__ __forceinline__ float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float f3dot(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 f3cross(float3 a, float3 b) {
+  return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 f3abs(float3 a) { return make_float3(fabsf(a.x), fabsf(a.y), fabsf(a.z)); }
+__device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.y, a.z, a.w); }
+
+__device__ __forceinline__ void finish_ray(Ray& r) {
+  r.d = f3sub(r.P, r.S);
+  r.ad = f3abs(r.d);
+  r.M = make_float3(r.S.x + 0.5f * r.d.x, r.S.y + 0.5f * r.d.y, r.S.z + 0.5f * r.d.z);
+  r.dn = sqrtf(r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z);
+}
+
+// Pixel ray: P = fl(fl(D + fl(u U)) + fl(v V)) per component, no contraction.
+__device__ __forceinline__ Ray cone_ray(const GeomView& g, int a, int i, int j) {
+  const float* f = g.frame + 12 * a;
+  float u = g.ut[i], v = g.vt[j];
+  Ray r;
+  r.S = make_float3(f[0], f[1], f[2]);
+  r.U = make_float3(f[6], f[7], f[8]);
+  r.V = make_float3(f[9], f[10], f[11]);
+  r.P.x = __fadd_rn(__fadd_rn(f[3], __fmul_rn(u, f[6])), __fmul_rn(v, f[9]));
+  r.P.y = __fadd_rn(__fadd_rn(f[4], __fmul_rn(u, f[7])), __fmul_rn(v, f[10]));
+  r.P.z = __fadd_rn(__fadd_rn(f[5], __fmul_rn(u, f[8])), __fmul_rn(v, f[11]));
+  finish_ray(r);
+  return r;
+}
+
+// Exact perturbed sign of the edge (p, q): returns sign + 1 in bits 0-1 and
+// the exact.h flags in bits 2-3.
+__device__ __noinline__ int slow_edge_sign(float3 S, float3 P, float3 U, float3 V, float3 p, float3 q) {
+  float s[3] = {S.x, S.y, S.z}, pp[3] = {P.x, P.y, P.z}, u[3] = {U.x, U.y, U.z}, v[3] = {V.x, V.y, V.z};
+  float a[3] = {p.x, p.y, p.z}, b[3] = {q.x, q.y, q.z};
+  unsigned flags = 0;
+  int sg = perturbed_edge_sign(s, pp, u, v, a, b, &flags);
+  return (sg + 1) | (int)(flags << 2);
+}
+
+__device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, LaneStats& st) {
+  if (fast != 2) return fast;
+  int res = slow_edge_sign(r.S, r.P, r.U, r.V, p, q);
+  st.fp64++;
+  if (res & (kFlagExact << 2)) st.exact++;
+  if (res & (kFlagPerturbed << 2)) st.pert++;
+  return (res & 3) - 1;
+}
+
+// Float32 estimate of sigma(p, q) = (q - p) . w with w = d x (p - S) and
+// W = |d| x |p - S| (the cross-product magnitudes); 2 = uncertain.
+__device__ __forceinline__ int fast_sign(float3 e, float3 w, float3 W) {
+  float E = e.x * w.x + e.y * w.y + e.z * w.z;
+  float B = kFilterRel * (fabsf(e.x) * W.x + fabsf(e.y) * W.y + fabsf(e.z) * W.z) + kFilterAbs;
+  return E > B ? 1 : (E < -B ? -1 : 2);
+}
+
+__device__ __forceinline__ void cross_pair(const Ray& r, float3 p, float3& w, float3& W) {
+  float3 pv = f3sub(p, r.S);
+  w = f3cross(r.d, pv);
+  float3 apv = f3abs(pv);
+  W = make_float3(r.ad.y * apv.z + r.ad.z * apv.y, r.ad.z * apv.x + r.ad.x * apv.z, r.ad.x * apv.y + r.ad.y * apv.x);
+}
+
+// Exact entry test for boundary face b (slots in outward order).
+__device__ bool enters_face(const MeshView& M, const Ray& r, int b, LaneStats& st) {
+  const float4* q = M.bfaces + 4 * (size_t)b;
+  float4 q0 = q[0], q1 = q[1], q2 = q[2];
+  float3 a0 = make_float3(q0.x, q0.y, q0.z), a1 = make_float3(q1.x, q1.y, q1.z), a2 = make_float3(q2.x, q2.y, q2.z);
+  float3 w, W;
+  cross_pair(r, a0, w, W);
+  int s0 = fast_sign(f3sub(a1, a0), w, W);
+  if (s0 == 1) return false;
+  cross_pair(r, a1, w, W);
+  int s1 = fast_sign(f3sub(a2, a1), w, W);
+  if (s1 == 1) return false;
+  cross_pair(r, a2, w, W);
+  int s2 = fast_sign(f3sub(a0, a2), w, W);
+  if (s2 == 1) return false;
+  if (resolve(s0, r, a0, a1, st) != -1) return false;
+  if (resolve(s1, r, a1, a2, st) != -1) return false;
+  return resolve(s2, r, a2, a0, st) == -1;
+}
+
+// Slab test against a padded box over the whole line (conservative).
+__device__ __forceinline__ bool line_hits_box(const Ray& r, float3 inv, const BvhNode& nd) {
+  float tmin = -INFINITY, tmax = INFINITY;
+  const float s[3] = {r.S.x, r.S.y, r.S.z};
+  const float d[3] = {r.d.x, r.d.y, r.d.z};
+  const float iv[3] = {inv.x, inv.y, inv.z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] == 0.0f) {
+      if (s[k] < nd.lo[k] || s[k] > nd.hi[k]) return false;
+    } else {
+      float t0 = (nd.lo[k] - s[k]) * iv[k];
+      float t1 = (nd.hi[k] - s[k]) * iv[k];
+      tmin = fmaxf(tmin, fminf(t0, t1));
+      tmax = fminf(tmax, fmaxf(t0, t1));
+    }
+  }
+  return tmin <= tmax;
+}
+
+// Entry search (Section II-E): depth-first over the boundary BVH with skip
+// links (no stack); the convex hull is entered through exactly one face, so
+// the first face passing the exact entry test is the answer.
+__device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
+  float3 inv = make_float3(1.0f / r.d.x, 1.0f / r.d.y, 1.0f / r.d.z);
+  int node = 0;
+  while (node >= 0) {
+    const float4* np = reinterpret_cast<const float4*>(M.bvh + node);
+    float4 n0 = np[0], n1 = np[1];
+    BvhNode nd;
+    nd.lo[0] = n0.x;
+    nd.lo[1] = n0.y;
+    nd.lo[2] = n0.z;
+    nd.skip = __float_as_int(n0.w);
+    nd.hi[0] = n1.x;
+    nd.hi[1] = n1.y;
+    nd.hi[2] = n1.z;
+    nd.leaf = __float_as_int(n1.w);
+    if (line_hits_box(r, inv, nd)) {
+      if (nd.leaf >= 0) {
+        int first = nd.leaf >> 3, cnt = nd.leaf & 7;
+        for (int i = 0; i < cnt; ++i)
+          if (enters_face(M, r, first + i, st)) return first + i;
+        node = nd.skip;
+      } else {
+        node = node + 1;
+      }
+    } else {
+      node = nd.skip;
+    }
+  }
+  return -1;
+}
+
+__device__ __forceinline__ unsigned remap_local(unsigned p, unsigned f, unsigned back) {
+  unsigned rank = p - (p > f ? 1u : 0u);
+  return rank + (rank >= back ? 1u : 0u);
+}
+
+template <int MODE>
+struct WalkOut {
+  // FWD
+  const float* x = nullptr;
+  double acc = 0.0;
+  // BWD / GATHER_FILL: weight = y_j * |d|
+  float weight = 0.f;
+  float* xhat = nullptr;
+  // TRACE / GATHER_FILL output cursor
+  int32_t* out_tet = nullptr;
+  float* out_len = nullptr;
+  int64_t cursor = 0;
+  const int* perm = nullptr;
+  // COUNT
+  int64_t count = 0;
+};
+
+// Walk one ray from boundary face `entry` to the boundary.
+template <int MODE>
+__device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int entry, WalkOut<MODE>& o,
+                                         LaneStats& st) {
+  const float4* bq = M.bfaces + 4 * (size_t)entry;
+  float4 q0 = bq[0], q1 = bq[1], q2 = bq[2], q3 = bq[3];
+  int tet = __float_as_int(q0.w);
+  unsigned lp = (unsigned)__float_as_int(q1.w);
+  unsigned loc = lp & 63u;          // local index of slot s in bits 2s..2s+1
+  unsigned locv = (lp >> 6) & 3u;   // local index of v
+  float3 a0 = make_float3(q0.x, q0.y, q0.z);
+  float3 a1 = make_float3(q1.x, q1.y, q1.z);
+  float3 a2 = make_float3(q2.x, q2.y, q2.z);
+  float3 v = make_float3(q3.x, q3.y, q3.z);
+  // Ray parameters are kept as s = t - 1/2 around the reference point M, and
+  // each segment is measured from the current entry point Q = M + s_in d, a
+  // point within one tetrahedron of the exit face, so the float32 rounding of
+  // (v - Q) . n stays proportional to the element size rather than to the
+  // source distance.  Only segment lengths are accumulated, never
+  // differences of rounded parameters.
+  float s_in;
+  {
+    float3 n = f3cross(f3sub(a1, a0), f3sub(a2, a0));
+    s_in = f3dot(f3sub(a0, r.M), n) / f3dot(r.d, n);
+    s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
+  }
+  float xcur = 0.f;
+  if constexpr (MODE == kModeForward) xcur = o.x[tet];
+  const int cap = M.nt + 1;
+  for (int step = 0;; ++step) {
+    if (step >= cap) {
+      st.failed++;
+      break;
+    }
+    float3 w, W;
+    cross_pair(r, v, w, W);
+    float3 e0 = f3sub(a0, v), e1 = f3sub(a1, v), e2 = f3sub(a2, v);
+    int s0 = fast_sign(e0, w, W);
+    int s1 = fast_sign(e1, w, W);
+    int s2 = fast_sign(e2, w, W);
+    if (s0 == 2) s0 = resolve(2, r, v, a0, st);
+    if (s1 == 2) s1 = resolve(2, r, v, a1, st);
+    if (s2 == 2) s2 = resolve(2, r, v, a2, st);
+    int k;
+    float3 ei, ej;
+    if (s0 < 0 && s1 > 0) {
+      k = 2;
+      ei = e0;
+      ej = e1;
+    } else if (s1 < 0 && s2 > 0) {
+      k = 0;
+      ei = e1;
+      ej = e2;
+    } else if (s2 < 0 && s0 > 0) {
+      k = 1;
+      ei = e2;
+      ej = e0;
+    } else {
+      st.failed++;
+      break;
+    }
+    float3 n = f3cross(ei, ej);
+    float3 Q = make_float3(r.M.x + s_in * r.d.x, r.M.y + s_in * r.d.y, r.M.z + s_in * r.d.z);
+    float dt = f3dot(f3sub(v, Q), n) / f3dot(r.d, n);
+    dt = fminf(fmaxf(dt, 0.0f), fmaxf(0.5f - s_in, 0.0f));
+    st.steps++;
+    if (dt == 0.f) st.zero++;
+    // Next tetrahedron across the exit face (local face index loc[k]).
+    unsigned f = (loc >> (2 * k)) & 3u;
+    float4 rec = M.faces[4 * (size_t)tet + f];
+    if constexpr (MODE == kModeForward) {
+      o.acc += (double)dt * (double)xcur;
+    } else if constexpr (MODE == kModeBackAtomic) {
+      if (dt > 0.f) unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
+    } else if constexpr (MODE == kModeCountAll) {
+      o.count++;
+    } else if constexpr (MODE == kModeCountPos) {
+      if (dt > 0.f) o.count++;
+    } else if constexpr (MODE == kModeTrace) {
+      o.out_tet[o.cursor] = o.perm[tet];
+      o.out_len[o.cursor] = dt * r.dn;
+      o.cursor++;
+    } else if constexpr (MODE == kModeGatherFill) {
+      if (dt > 0.f) {
+        o.out_tet[o.cursor] = tet;
+        o.out_len[o.cursor] = dt * o.weight;
+        o.cursor++;
+      }
+    }
+    int packed = __float_as_int(rec.x);
+    if (packed < 0) break;
+    unsigned back = (unsigned)packed & 3u;
+    unsigned nl0 = remap_local((loc >> 0) & 3u, f, back);
+    unsigned nl1 = remap_local((loc >> 2) & 3u, f, back);
+    unsigned nl2 = remap_local((loc >> 4) & 3u, f, back);
+    unsigned nv_ = remap_local(locv, f, back);
+    if (k == 0) {
+      nl0 = nv_;
+      a0 = v;
+    } else if (k == 1) {
+      nl1 = nv_;
+      a1 = v;
+    } else {
+      nl2 = nv_;
+      a2 = v;
+    }
+    loc = nl0 | (nl1 << 2) | (nl2 << 4);
+    locv = back;
+    v = xyz(rec);
+    tet = packed >> 2;
+    s_in += dt;
+    if constexpr (MODE == kModeForward) xcur = o.x[tet];
+  }
+}
+
+__device__ __forceinline__ void flush_stats(const MeshView& M, LaneStats& st, int active) {
+  // Wave-level reduction, one atomic per counter per wave.
+  int v[7] = {active, st.steps, st.zero, st.fp64, st.exact, st.pert, st.failed};
+#pragma unroll
+  for (int c = 0; c < 7; ++c) {
+    int x = v[c];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    v[c] = x;
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c)
+      if (v[c]) atomicAdd(M.counters + c, (unsigned long long)v[c]);
+  }
+}
+
+struct TileMap {
+  int tile_u, tile_v, ntu, ntv;
+};
+
+// Map (wave, lane) to a pixel ray; returns false for lanes off the detector.
+__device__ __forceinline__ bool tile_ray(const GeomView& g, const TileMap& tm, int64_t wave, int lane, int a0,
+                                         int na_chunk, int* a, int* i, int* j) {
+  int64_t per_angle = (int64_t)tm.ntu * tm.ntv;
+  int64_t aa = wave / per_angle;
+  int64_t rem = wave - aa * per_angle;
+  int tv = (int)(rem / tm.ntu), tu = (int)(rem - (int64_t)tv * tm.ntu);
+  *a = a0 + (int)aa;
+  *i = tu * tm.tile_u + lane % tm.tile_u;
+  *j = tv * tm.tile_v + lane / tm.tile_u;
+  return aa < na_chunk && *i < g.nu && *j < g.nv;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- kernels
+
+// One launch per mode over the pixel rays of angles [a0, a0 + na_chunk).
+//   kModeEntry:      out_i32[rid] = entry face (or -1)
+//   kModeForward:    out_f32[rid] = sum_i a_ij x_i
+//   kModeBackAtomic: xhat[i] += a_ij y_j
+//   kModeCountPos:   counts[rid - rid0] = positive-length visits
+//   kModeGatherFill: keys/vals at offsets[rid - rid0]
+template <int MODE>
+__global__ __launch_bounds__(256) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
+                                                         const int32_t* entry, const float* in, float* out_f32,
+                                                         int32_t* out_i32, int64_t* counts, const int64_t* offsets,
+                                                         int32_t* keys, float* vals) {
+  int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  int a, i, j;
+  bool active = tile_ray(G, tm, wave, lane, a0, na_chunk, &a, &i, &j);
+  LaneStats st;
+  if (active) {
+    int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
+    int64_t rid0 = (int64_t)a0 * G.nv * G.nu;
+    Ray r = cone_ray(G, a, i, j);
+    int e = (entry && MODE != kModeEntry) ? entry[rid] : find_entry(M, r, st);
+    if constexpr (MODE == kModeEntry) {
+      out_i32[rid] = e;
+    } else if constexpr (MODE == kModeForward) {
+      WalkOut<MODE> o;
+      o.x = in;
+      if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+      out_f32[rid] = (float)(o.acc * (double)r.dn);
+    } else if constexpr (MODE == kModeBackAtomic) {
+      WalkOut<MODE> o;
+      o.xhat = out_f32;
+      o.weight = in[rid] * r.dn;
+      if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, e, o, st);
+    } else if constexpr (MODE == kModeCountPos) {
+      WalkOut<MODE> o;
+      if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+      counts[rid - rid0] = o.count;
+    } else if constexpr (MODE == kModeGatherFill) {
+      WalkOut<MODE> o;
+      o.weight = in[rid] * r.dn;
+      o.out_tet = keys;
+      o.out_len = vals;
+      o.cursor = offsets[rid - rid0];
+      if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+    }
+  }
+  flush_stats(M, st, active ? 1 : 0);
+}
+
+// Listed rays (trace): either pixel ray ids, or explicit S/P/U/V arrays.
+template <int MODE>
+__global__ __launch_bounds__(256) void list_walk_kernel(MeshView M, GeomView G, const int64_t* ids, const float* S,
+                                                        const float* P, const float* U, const float* V, int32_t n,
+                                                        int64_t* counts, const int64_t* offsets, int32_t* tets,
+                                                        float* lens) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  LaneStats st;
+  bool active = k < n;
+  if (active) {
+    Ray r;
+    if (ids) {
+      int64_t rid = ids[k];
+      int i = (int)(rid % G.nu);
+      int j = (int)((rid / G.nu) % G.nv);
+      int a = (int)(rid / ((int64_t)G.nu * G.nv));
+      r = cone_ray(G, a, i, j);
+    } else {
+      r.S = make_float3(S[3 * k], S[3 * k + 1], S[3 * k + 2]);
+      r.P = make_float3(P[3 * k], P[3 * k + 1], P[3 * k + 2]);
+      r.U = make_float3(U[3 * k], U[3 * k + 1], U[3 * k + 2]);
+      r.V = make_float3(V[3 * k], V[3 * k + 1], V[3 * k + 2]);
+      finish_ray(r);
+    }
+    // {P - S, U, V} must be a basis for the tie-breaking translation.
+    float s3[3] = {r.S.x, r.S.y, r.S.z}, p3[3] = {r.P.x, r.P.y, r.P.z}, u3[3] = {r.U.x, r.U.y, r.U.z},
+          v3[3] = {r.V.x, r.V.y, r.V.z};
+    bool basis = det_diff_sign(p3, s3, u3, nullptr, v3, nullptr, nullptr) != 0;
+    int e = basis ? find_entry(M, r, st) : -1;
+    if (!basis) st.failed++;
+    WalkOut<MODE> o;
+    if constexpr (MODE == kModeTrace) {
+      o.out_tet = tets;
+      o.out_len = lens;
+      o.perm = M.perm;
+      o.cursor = offsets[k];
+    }
+    if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+    if constexpr (MODE == kModeCountAll) counts[k] = o.count;
+  }
+  flush_stats(M, st, active ? 1 : 0);
+}
+
+__global__ void fill_f32_kernel(float* p, int64_t n, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void permute_kernel(const float* in, float* out, const int32_t* perm, int n, int scatter) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (scatter)
+    out[perm[i]] = in[i];
+  else
+    out[i] = in[perm[i]];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static TileMap make_tiles(const GeomView& g, int tile_u) {
+  TileMap t;
+  t.tile_u = tile_u;
+  t.tile_v = 64 / tile_u;
+  t.ntu = (g.nu + t.tile_u - 1) / t.tile_u;
+  t.ntv = (g.nv + t.tile_v - 1) / t.tile_v;
+  return t;
+}
+
+tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
+                             const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
+                             int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
+                             hipStream_t s) {
+  MeshView M = m->view();
+  GeomView G = g->view();
+  TileMap tm = make_tiles(G, tile_u);
+  int64_t waves = (int64_t)tm.ntu * tm.ntv * na_chunk;
+  int64_t blocks = (waves + 3) / 4;
+  if (blocks <= 0) return TCT_OK;
+  if (blocks > 0x7fffffff) {
+    set_error("too many rays in one launch");
+    return TCT_E_ARG;
+  }
+  dim3 grid((unsigned)blocks), block(256);
+  switch (mode) {
+    case kModeEntry:
+      hipLaunchKernelGGL(pixel_walk_kernel<kModeEntry>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
+                         out_f32, out_i32, counts, offsets, keys, vals);
+      break;
+    case kModeForward:
+      hipLaunchKernelGGL(pixel_walk_kernel<kModeForward>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
+                         out_f32, out_i32, counts, offsets, keys, vals);
+      break;
+    case kModeBackAtomic:
+      hipLaunchKernelGGL(pixel_walk_kernel<kModeBackAtomic>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
+                         out_f32, out_i32, counts, offsets, keys, vals);
+      break;
+    case kModeCountPos:
+      hipLaunchKernelGGL(pixel_walk_kernel<kModeCountPos>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
+                         out_f32, out_i32, counts, offsets, keys, vals);
+      break;
+    case kModeGatherFill:
+      hipLaunchKernelGGL(pixel_walk_kernel<kModeGatherFill>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
+                         out_f32, out_i32, counts, offsets, keys, vals);
+      break;
+    default:
+      set_error("bad walk mode");
+      return TCT_E_ARG;
+  }
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+tct_status launch_list_walk(int mode, const tct_mesh* m, const tct_geom* g, const int64_t* ids, const float* S,
+                            const float* P, const float* U, const float* V, int32_t n, int64_t* counts,
+                            const int64_t* offsets, int32_t* tets, float* lens, hipStream_t s) {
+  if (n <= 0) return TCT_OK;
+  MeshView M = m->view();
+  GeomView G{};
+  if (g) G = g->view();
+  dim3 grid((n + 255) / 256), block(256);
+  if (mode == kModeCountAll)
+    hipLaunchKernelGGL(list_walk_kernel<kModeCountAll>, grid, block, 0, s, M, G, ids, S, P, U, V, n, counts, offsets,
+                       tets, lens);
+  else
+    hipLaunchKernelGGL(list_walk_kernel<kModeTrace>, grid, block, 0, s, M, G, ids, S, P, U, V, n, counts, offsets,
+                       tets, lens);
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+tct_status launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return TCT_OK;
+  hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s) {
+  if (n <= 0) return TCT_OK;
+  hipLaunchKernelGGL(permute_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, perm, n, scatter);
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+}  // namespace tct

@@ -1,0 +1,307 @@
+"""GPU parity: the HIP walk (through the C ABI) against the CPU oracle.
+
+Bars (float32 path vs float64 oracle):
+  * traversed-tetrahedron sequences, zero-length passages included: identical;
+  * segment lengths: |L_gpu - L_ref| <= 1e-5 * chord of the ray;
+  * projections: |b_gpu - b_ref| <= 1e-5 * sum_i a_ij |x_i|; misses exactly 0;
+  * backprojections: |dxhat_i| <= 1e-5 * sum_{j: a_ij>0} chord_j |y_j|
+    + n_i 2^-24 (A^T|y|)_i (n_i = terms summed into element i, float32
+    accumulation), and l2-relative <= 1e-5;
+  * adjoint: |<Ax,y> - <x,A^T y>| <= 1e-5 <|A||x|, |y|>.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from golden_io import load_worked_example
+
+pytestmark = pytest.mark.gpu
+
+f32 = np.float32
+DEV = "cuda:0"
+
+
+def _gpu():
+    import paper_1908_06909_amd as tct
+
+    return tct
+
+
+class Case:
+    """Mesh + geometry on both sides."""
+
+    def __init__(self, w):
+        tct = _gpu()
+        self.w = w
+        self.orc = oracle.Oracle(w.verts, w.tets, w.cone, w.angles)
+        self.mesh = tct.TetMesh(w.verts, w.tets, device=DEV)
+        self.geom = tct.ConeGeometry(w.cone, w.angles, device=DEV)
+        self.P = tct.Projector(self.mesh, self.geom)
+
+    def x_internal(self, x_user):
+        return self.mesh.to_internal(torch.as_tensor(np.ascontiguousarray(x_user, f32), device=DEV))
+
+    def to_user(self, x_int):
+        return self.mesh.to_user(x_int).cpu().numpy()
+
+
+_cases = {}
+
+
+def case(name):
+    if name not in _cases:
+        if name == "cfg0":
+            w = synth.config(0)
+        elif name == "cfg1":
+            w = synth.config(1)
+        elif name == "cfg2":
+            w = synth.config(2)
+        elif name == "graded_small":
+            (verts, tets), X, Z = synth.graded_mesh(24, 8, 1.05, 17)
+            x = synth.sphere_phantom(verts, tets, 12)
+            du = 2.0 ** -5
+            cone = synth.Cone(4.0, 8.0, 64, 64, du, du, du / 2, du / 2)
+            w = synth.Workload("graded24", verts, tets, x, cone, synth.angles_for(12))
+        elif name == "ragged":
+            w = synth.jittered_kuhn(5, 7, 8, 37, 29, 5)
+            w.cone = synth.Cone(4.0, 8.0, 37, 29, 0.08, 0.09, 0.013, -0.021)  # wider than the mesh shadow
+        else:
+            raise KeyError(name)
+        _cases[name] = Case(w)
+    return _cases[name]
+
+
+def compare_traces(gpu, ref):
+    assert len(gpu) == len(ref)
+    for k, ((gt, gl), (rt, rl)) in enumerate(zip(gpu, ref)):
+        assert np.array_equal(gt, rt), f"ray {k}: sequences differ\n gpu {gt[:40]}\n ref {rt[:40]}"
+        chord = float(rl.sum())
+        assert np.all(np.abs(gl.astype(np.float64) - rl) <= 1e-5 * max(chord, 1e-30)), f"ray {k}: lengths"
+
+
+def check_stats(mesh):
+    st = mesh.stats(reset=True)
+    assert st["failed"] == 0, st
+    return st
+
+
+# ---------------------------------------------------------------- cfg0 (full)
+def test_cfg0_all_sequences_bitexact():
+    c = case("cfg0")
+    ids = np.arange(c.orc.nrays)
+    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    check_stats(c.mesh)
+
+
+def test_cfg0_forward():
+    c = case("cfg0")
+    x = c.w.x
+    ref = c.orc.forward(x)
+    xi = c.x_internal(x)
+    got = c.P.forward(xi).cpu().numpy().ravel()
+    got_nc = c.P.forward(xi, use_cache=False).cpu().numpy().ravel()
+    assert np.array_equal(got, got_nc), "entry cache changes the result"
+    tol = 1e-5 * c.orc.forward(np.abs(x))
+    assert np.all(np.abs(got - ref) <= tol + 1e-30)
+    assert np.all(got[ref == 0] == 0)
+    check_stats(c.mesh)
+
+
+def _bp_tolerance(c, y):
+    """Per-element tolerance and term counts from the oracle's full trace."""
+    ids = np.arange(c.orc.nrays)
+    tr = c.orc.trace(ids)
+    nt = c.orc.nt
+    chord_w = np.zeros(nt)
+    nterm = np.zeros(nt)
+    for j, (tt, ll) in enumerate(tr):
+        pos = ll > 0
+        np.add.at(chord_w, tt[pos], ll.sum() * abs(float(y[j])))
+        np.add.at(nterm, tt[pos], 1)
+    absbp = c.orc.backproject(np.abs(y))
+    return 1e-5 * chord_w + nterm * 2.0 ** -24 * absbp + 1e-30
+
+
+@pytest.mark.parametrize("mode", ["atomic", "gather"])
+def test_cfg0_backproject(mode):
+    c = case("cfg0")
+    rng = np.random.default_rng(31)
+    y = rng.uniform(-1, 1, c.orc.nrays).astype(f32)
+    ref = c.orc.backproject(y)
+    yt = torch.as_tensor(y, device=DEV)
+    got = c.to_user(c.P.backproject(yt, mode=mode)).astype(np.float64)
+    tol = _bp_tolerance(c, y)
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), f"{bad.sum()} elements out of tolerance; worst {np.max(np.abs(got-ref)/tol)}"
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    check_stats(c.mesh)
+
+
+def test_cfg0_gather_is_deterministic_and_accumulates():
+    c = case("cfg0")
+    rng = np.random.default_rng(32)
+    yt = torch.as_tensor(rng.uniform(-1, 1, c.orc.nrays).astype(f32), device=DEV)
+    a = c.P.backproject(yt, mode="gather").cpu().numpy()
+    b = c.P.backproject(yt, mode="gather").cpu().numpy()
+    assert np.array_equal(a.view(np.int32), b.view(np.int32))
+    base = torch.full((c.orc.nt,), 0.25, dtype=torch.float32, device=DEV)
+    acc = c.P.backproject(yt, mode="gather", out=base.clone(), accumulate=True).cpu().numpy()
+    assert np.allclose(acc, a + np.float32(0.25), rtol=0, atol=1e-6)
+    acc2 = c.P.backproject(yt, mode="atomic", out=base.clone(), accumulate=True).cpu().numpy()
+    assert np.allclose(acc2, acc, rtol=1e-5, atol=1e-5)
+
+
+def test_cfg0_adjoint():
+    c = case("cfg0")
+    rng = np.random.default_rng(33)
+    x = rng.uniform(-1, 1, c.orc.nt).astype(f32)
+    y = rng.uniform(-1, 1, c.orc.nrays).astype(f32)
+    xi = c.x_internal(x)
+    Ax = c.P.forward(xi).cpu().numpy().ravel().astype(np.float64)
+    for mode in ("atomic", "gather"):
+        Aty = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode)).astype(np.float64)
+        lhs = float(np.dot(Ax, y))
+        rhs = float(np.dot(x.astype(np.float64), Aty))
+        scale = float(np.dot(c.orc.forward(np.abs(x)), np.abs(y)))
+        assert abs(lhs - rhs) <= 1e-5 * scale, (mode, lhs, rhs)
+
+
+# ---------------------------------------------------------------- custom rays
+@pytest.mark.parametrize("name", ["W1_kuhn1_diagonal.txt", "W2_kuhn4_axis.txt"])
+def test_worked_examples_gpu(name):
+    tct = _gpu()
+    g = load_worked_example(name)
+    X = synth.kuhn_nodes(g["n"])
+    verts, tets = synth.kuhn_mesh(X, X, X)
+    m = tct.TetMesh(verts, tets, device=DEV)
+    (tt, ll), = tct.trace_rays(m, *[np.asarray(a)[None] for a in g["ray"]])
+    assert list(tt) == list(g["tets"])
+    assert np.allclose(ll, g["lengths"], rtol=0, atol=1e-5)
+    check_stats(m)
+
+
+def _degenerate_rays():
+    ex, ey, ez = np.eye(3, dtype=f32)
+    rays = []
+    for y in (-0.25, 0.0, 0.125, 0.25):
+        for z in (-0.25, 0.0, 0.25, 0.3):
+            rays.append((np.array([4, y, z], f32), np.array([-4, y, z], f32), ey, ez))
+            rays.append((np.array([y, -4, z], f32), np.array([y, 4, z], f32), ez, ex))
+            rays.append((np.array([y, z, 4], f32), np.array([y, z, -4], f32), ex, -ey))
+    for U, V in ((ex, ey), (ey, ex), (ez, ex), (-ex, ez)):
+        rays.append((np.array([-2, -2, -2], f32), np.array([2, 2, 2], f32), U, V))
+        rays.append((np.array([-2, -2, 0], f32), np.array([2, 2, 0], f32), U, V))
+        rays.append((np.array([-2, 0.25, -2], f32), np.array([2, 0.25, 2], f32), U, V))
+        rays.append((np.array([2, -2, 0.25], f32), np.array([-2, 2, 0.25], f32), U, V))
+    # grazing the hull: along a hull edge and inside a hull face plane
+    rays.append((np.array([4, 0.5, 0.5], f32), np.array([-4, 0.5, 0.5], f32), ey, ez))
+    rays.append((np.array([4, -0.5, 0.1], f32), np.array([-4, -0.5, 0.1], f32), ey, ez))
+    rays.append((np.array([4, 0.5, 0.1], f32), np.array([-4, 0.5, 0.1], f32), -ey, ez))
+    # missing the hull
+    rays.append((np.array([4, 0.9, 0.1], f32), np.array([-4, 0.9, 0.1], f32), ey, ez))
+    import exact_ref
+
+    return [r for r in rays if exact_ref.orient3d(np.zeros(3, f32), r[1] - r[0], r[2], r[3]) != 0]
+
+
+def test_degenerate_custom_rays_match_oracle():
+    tct = _gpu()
+    X = synth.kuhn_nodes(4)
+    verts, tets = synth.kuhn_mesh(X, X, X)
+    m = tct.TetMesh(verts, tets, device=DEV)
+    om = oracle.OracleMesh(verts, tets)
+    rays = _degenerate_rays()
+    S, P, U, V = (np.array([r[k] for r in rays], f32) for k in range(4))
+    compare_traces(tct.trace_rays(m, S, P, U, V), oracle.oracle.trace_rays(om, S, P, U, V))
+    st = check_stats(m)
+    assert st["perturbed_ties"] > 0 and st["exact_stage"] > 0
+
+
+def test_trace_empty_list():
+    c = case("cfg0")
+    assert c.P.trace(np.zeros(0, np.int64)) == []
+
+
+# ---------------------------------------------------------------- graded / cfg2
+def _degenerate_ids(nu, nv, na, stride_a=1):
+    cu, cv = (nu - 1) // 2, (nv - 1) // 2
+    ids = []
+    for a in range(0, na, stride_a):
+        base = a * nu * nv
+        ids += [base + cv * nu + i for i in range(nu)]  # central row: inside the plane z = 0
+        ids += [base + j * nu + cu for j in range(nv)]  # central column: crosses the z axis
+    return np.array(sorted(set(ids)), np.int64)
+
+
+def test_graded_small_all_sequences():
+    c = case("graded_small")
+    ids = np.arange(c.orc.nrays)
+    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    xi = c.x_internal(c.w.x)
+    got = c.P.forward(xi).cpu().numpy().ravel()
+    ref = c.orc.forward(c.w.x)
+    assert np.all(np.abs(got - ref) <= 1e-5 * c.orc.forward(np.abs(c.w.x)) + 1e-30)
+    st = check_stats(c.mesh)
+    assert st["perturbed_ties"] > 0
+
+
+def test_cfg2_sampled_sequences_and_forward():
+    c = case("cfg2")
+    cone = c.w.cone
+    rng = np.random.default_rng(2)
+    ids = np.concatenate([_degenerate_ids(cone.nu, cone.nv, len(c.w.angles), stride_a=45),
+                          rng.integers(0, c.orc.nrays, 1500)])
+    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    xi = c.x_internal(c.w.x)
+    full = c.P.forward(xi).cpu().numpy().ravel()
+    ref = c.orc.forward(c.w.x, ids)
+    tol = 1e-5 * c.orc.forward(np.abs(c.w.x), ids)
+    assert np.all(np.abs(full[ids] - ref) <= tol + 1e-30)
+    check_stats(c.mesh)
+
+
+# ---------------------------------------------------------------- cfg1 (full size, sampled)
+def test_cfg1_sampled_sequences_and_forward():
+    c = case("cfg1")
+    rng = np.random.default_rng(1)
+    n_per = c.w.cone.nu * c.w.cone.nv
+    ids = np.concatenate([rng.integers(0, c.orc.nrays, 2500), 100 * n_per + 256 * 512 + np.arange(512)])
+    compare_traces(c.P.trace(ids[:800]), c.orc.trace(ids[:800]))
+    xi = c.x_internal(c.w.x)
+    full = c.P.forward(xi).cpu().numpy().ravel()
+    ref = c.orc.forward(c.w.x, ids)
+    tol = 1e-5 * c.orc.forward(np.abs(c.w.x), ids)
+    assert np.all(np.abs(full[ids] - ref) <= tol + 1e-30)
+    assert np.all(full != 0)  # every ray of this geometry hits the cube
+    check_stats(c.mesh)
+
+
+# ---------------------------------------------------------------- edges
+def test_ragged_detector_and_missing_rays():
+    c = case("ragged")
+    ids = np.arange(c.orc.nrays)
+    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    xi = c.x_internal(c.w.x)
+    got = c.P.forward(xi).cpu().numpy().ravel()
+    ref = c.orc.forward(c.w.x)
+    assert (ref == 0).sum() > 0, "geometry should include rays that miss"
+    assert np.all(got[ref == 0] == 0)
+    assert np.all(np.abs(got - ref) <= 1e-5 * c.orc.forward(np.abs(c.w.x)) + 1e-30)
+    y = np.random.default_rng(3).uniform(0, 1, c.orc.nrays).astype(f32)
+    bp = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode="gather"))
+    assert np.linalg.norm(bp - c.orc.backproject(y)) <= 1e-5 * np.linalg.norm(c.orc.backproject(y))
+    check_stats(c.mesh)
+
+
+def test_geometry_rejected_when_mesh_not_between_source_and_detector():
+    tct = _gpu()
+    X = synth.kuhn_nodes(2)
+    verts, tets = synth.kuhn_mesh(X, X, X)
+    m = tct.TetMesh(verts * f32(10), tets, device=DEV)
+    g = tct.ConeGeometry(synth.Cone(4.0, 8.0, 8, 8, 0.25, 0.25), synth.angles_for(2), device=DEV)
+    with pytest.raises(tct._lib.TctError) as e:
+        tct.Projector(m, g)
+    assert e.value.status == -6
