@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the tetrahedral projector's hot path on one MI355X.
+
+Workload: jittered Kuhn 64^3 mesh of the unit cube (1,572,864 tetrahedra),
+sphere phantom, cone beam DSO 4 / DSD 8, 512 x 512 detector, 360 angles
+(94,371,840 rays).  One step = entry search for every ray (boundary BVH,
+cached for the step) + forward projection A x + atomic backprojection
+A^T b of that projection.  The value is tet-segments (walk steps, zero-length
+passages included) per second over both walks.
+
+Prints one JSON line.  Options: --steps K (timed), --warmup W, --gpus N (1
+only), --no-cpu-baseline, --gather (also time the deterministic gather
+backprojection), --json-extra FILE (write per-kernel details).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+FWD_BYTES_PER_SEG = 24  # neighbour id + new vertex id + its xyz + x_i
+BWD_BYTES_PER_SEG = 28  # walk geometry (20) + read-modify-write of xhat_i (8)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=1, help="workload index (1 = the benchmark configuration)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--gather", action="store_true")
+    ap.add_argument("--json-extra", default=None)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle (float64, exact signs) on every k-th ray of the workload,
+    forward + backprojection, on all host threads; extrapolated to seg/s."""
+    import oracle
+
+    t0 = time.time()
+    o = oracle.Oracle(w.verts, w.tets, w.cone, w.angles)
+    build_s = time.time() - t0
+    n = o.nrays
+    # First a small probe to size the sample for the time budget.
+    probe = np.arange(0, n, max(1, n // 2000), dtype=np.int64)
+    t0 = time.time()
+    _, cnt = o.forward(w.x, probe, return_counts=True)
+    dt = max(time.time() - t0, 1e-3)
+    rate = cnt.sum() / dt
+    seg_per_ray = max(cnt.mean(), 1.0)
+    want = int(budget_s * 0.5 * rate / seg_per_ray)
+    k = max(1, n // max(want, 1))
+    ids = np.arange(0, n, k, dtype=np.int64)
+    t0 = time.time()
+    b, cnt = o.forward(w.x, ids, return_counts=True)
+    t1 = time.time()
+    o.backproject(b.astype(np.float32), ids)
+    t2 = time.time()
+    segs = 2 * int(cnt.sum())
+    threads = oracle.oracle.max_threads() if o.nthreads == 0 else o.nthreads
+    return {
+        "value": segs / (t2 - t0),
+        "unit": "tet-segments/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"every {k}-th ray ({len(ids)} rays, {segs} segments fwd+back) of the same workload; "
+                  f"forward {t1 - t0:.1f}s, backprojection {t2 - t1:.1f}s; mesh build {build_s:.1f}s untimed",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md "
+                                   "and not launched", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_1908_06909_amd import ConeGeometry, Projector, TetMesh
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.config(args.workload)
+    t0 = time.time()
+    mesh = TetMesh(w.verts, w.tets, device=dev)
+    geom = ConeGeometry(w.cone, w.angles, device=dev)
+    ingest_s = time.time() - t0
+    P = Projector(mesh, geom, cache_entry=False)
+    x = mesh.to_internal(torch.as_tensor(w.x, device=dev))
+    entry = torch.empty(geom.nrays, dtype=torch.int32, device=dev)
+    proj = torch.empty(geom.shape, dtype=torch.float32, device=dev)
+    xhat = torch.empty(mesh.nt, dtype=torch.float32, device=dev)
+
+    ev = {k: [] for k in ("entry", "forward", "backproject")}
+
+    def step(record):
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        P.compute_entry(entry)
+        e1.record(s)
+        P.entry = entry
+        P.forward(x, out=proj)
+        e2.record(s)
+        P.backproject(proj, mode="atomic", out=xhat)
+        e3.record(s)
+        if record:
+            ev["entry"].append((e0, e1))
+            ev["forward"].append((e1, e2))
+            ev["backproject"].append((e2, e3))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    mesh.stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = mesh.stats(reset=True)
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    # Segments per walk: the counters hold forward + backprojection walks of
+    # every timed step (the entry pass walks nothing).
+    segs_total = st["segments"]
+    segs_per_walk = segs_total / (2 * args.steps)
+    value = segs_total / elapsed
+    fwd_gbs = FWD_BYTES_PER_SEG * segs_per_walk / (ms["forward"] * 1e-3) / 1e9
+    bwd_gbs = BWD_BYTES_PER_SEG * segs_per_walk / (ms["backproject"] * 1e-3) / 1e9
+    if ms["forward"] >= ms["backproject"]:
+        dom, ach, bps = "forward walk (pixel_walk_kernel<1>)", fwd_gbs, FWD_BYTES_PER_SEG
+    else:
+        dom, ach, bps = "atomic backprojection walk (pixel_walk_kernel<2>)", bwd_gbs, BWD_BYTES_PER_SEG
+    out = {
+        "metric": "tet-segments/s fwd+back at 1 GPU",
+        "value": value,
+        "unit": "tet-segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "tets": mesh.nt,
+            "rays": geom.nrays,
+            "detector": [w.cone.nv, w.cone.nu],
+            "angles": len(w.angles),
+            "segments_per_walk": segs_per_walk,
+            "step": "entry search + forward + atomic backprojection",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": ach,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_segment": bps,
+        },
+        "kernels_ms": ms,
+        "walk_stats": st,
+        "ingest_s": ingest_s,
+    }
+    # The other backprojection variants, one timed call each (not part of the step).
+    for mode in ("atomic_direct",) + (("gather",) if args.gather else ()):
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record()
+        P.backproject(proj, mode=mode, out=xhat)
+        g1.record()
+        torch.cuda.synchronize()
+        t_ms = g0.elapsed_time(g1)
+        out.setdefault("variants", {})[mode] = {"ms": t_ms, "seg_per_s": segs_per_walk / (t_ms * 1e-3)}
+    mesh.stats(reset=True)
+    if False:
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record()
+        P.backproject(proj, mode="gather", out=xhat)
+        g1.record()
+        torch.cuda.synchronize()
+        out["gather_ms"] = g0.elapsed_time(g1)
+        out["gather_seg_per_s"] = segs_per_walk / (out["gather_ms"] * 1e-3)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    if args.json_extra:
+        with open(args.json_extra, "w") as f:
+            json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

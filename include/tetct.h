@@ -164,13 +164,17 @@ tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_s
 tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
                        tct_stream s);
 
-#define TCT_BP_ATOMIC 0 /* float32 atomic scatter along each ray (Section II-F) */
-#define TCT_BP_GATHER 1 /* deterministic: per-tetrahedron lists of (ray, length), summed in ray order */
+#define TCT_BP_ATOMIC 0        /* ray-driven float32 scatter (Section II-F); each 16x16-pixel block first sums
+                                  its segments per tetrahedron in on-chip memory, then adds one atomic per
+                                  distinct tetrahedron to xhat */
+#define TCT_BP_GATHER 1        /* deterministic: per-tetrahedron lists of (ray, length), summed in ray order */
+#define TCT_BP_ATOMIC_DIRECT 2 /* one float32 atomic add to xhat per segment, as in the paper */
 
 /* Backprojection xhat_i = sum_j a_ij y_j (Eq. 3 with the detector index on y).
  *   proj  device float [na][nv][nu]
  *   xhat  device float [nt], internal order; overwritten unless accumulate != 0
- *   mode  TCT_BP_ATOMIC or TCT_BP_GATHER.  GATHER gives bitwise-identical results
+ *   mode  TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT or TCT_BP_GATHER.  The atomic modes
+ *         sum in a run-dependent order.  GATHER gives bitwise-identical results
  *         run to run; it allocates stream-ordered scratch and synchronises the
  *         stream once per angle chunk. */
 tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
@@ -192,6 +196,38 @@ tct_status tct_trace(const tct_mesh* m, const tct_geom* g, const int64_t* ray_id
 tct_status tct_trace_rays(const tct_mesh* m, const float* S, const float* P, const float* U, const float* V,
                           int32_t n, int64_t* offsets, int32_t* tets, float* lengths, int64_t cap, int64_t* needed,
                           tct_stream s);
+
+/* ---------------------------------------------------------------- solver vectors
+ * Building blocks for iterative reconstruction with A and A^T (the paper names
+ * SART and CGLS as consumers of the projector, Section II-A; it reconstructs
+ * with OS-SART, Section III-A).  All arrays are device memory of n floats;
+ * scalars passed as `const double*` are device pointers, so an iteration
+ * needs no host round trip and can be captured in a graph. */
+
+#define TCT_DOT_WORKSPACE 512 /* doubles of workspace tct_dot needs */
+
+/* result[0] (device double) = sum_i a_i b_i, accumulated in double in a fixed
+ * order (bitwise reproducible).  workspace: device double [TCT_DOT_WORKSPACE]. */
+tct_status tct_dot(const float* a, const float* b, int64_t n, double* result, double* workspace, tct_stream s);
+
+/* y += sign * (num[0] / den[0]) * x; a zero denominator gives a zero step. */
+tct_status tct_axpy_ratio(float* y, const float* x, int64_t n, const double* num, const double* den, double sign,
+                          tct_stream s);
+
+/* p = x + (num[0] / den[0]) * p; a zero denominator gives p = x. */
+tct_status tct_xpay_ratio(float* p, const float* x, int64_t n, const double* num, const double* den, tct_stream s);
+
+/* y = a * x + b * y (host scalars). */
+tct_status tct_axpby(float* y, const float* x, int64_t n, float a, float b, tct_stream s);
+
+/* y = a .* b (elementwise; y may alias a or b). */
+tct_status tct_mul(float* y, const float* a, const float* b, int64_t n, tct_stream s);
+
+/* y = (a > eps) ? 1 / a : 0 (elementwise; y may alias a). */
+tct_status tct_recip(float* y, const float* a, int64_t n, float eps, tct_stream s);
+
+/* dst[0..n) = src[0..n) for device doubles (solver scalars). */
+tct_status tct_copy_f64(double* dst, const double* src, int32_t n, tct_stream s);
 
 /* ---------------------------------------------------------------- misc */
 

@@ -673,6 +673,9 @@ const char* orc_last_error(void) { return g_err.c_str(); }
 
 long long orc_exact_calls(void) { return g_exact_calls.load(); }
 
+// Threads the parallel loops use when nthreads = 0.
+int orc_max_threads(void) { return nthreads_of(0); }
+
 // Last operation's walk statistics: rays, hits, segments, zero-length,
 // failed, multi-entry, perturbed signs, parallel-edge signs.
 void orc_last_stats(long long* out8) {

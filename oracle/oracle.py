@@ -72,6 +72,11 @@ def lib():
     return L
 
 
+def max_threads() -> int:
+    """Threads the oracle's parallel loops use by default."""
+    return int(lib().orc_max_threads())
+
+
 def _f3(v):
     return np.ascontiguousarray(np.asarray(v, dtype=np.float32).reshape(3))
 

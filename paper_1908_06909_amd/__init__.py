@@ -9,3 +9,7 @@ this package only marshals arguments.
 from .projector import ConeGeometry, Projector, TetMesh, trace_rays
 
 __all__ = ["TetMesh", "ConeGeometry", "Projector", "trace_rays"]
+
+from .solvers import CGLS, TetProject, cgls, project, sirt  # noqa: E402
+
+__all__ += ["TetProject", "project", "CGLS", "cgls", "sirt"]

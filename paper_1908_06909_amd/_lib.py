@@ -30,6 +30,8 @@ TCT_MESH_NO_REORDER = 1
 TCT_MESH_HOST_ONLY = 2
 TCT_BP_ATOMIC = 0
 TCT_BP_GATHER = 1
+TCT_BP_ATOMIC_DIRECT = 2
+TCT_DOT_WORKSPACE = 512
 
 
 class TctError(RuntimeError):
@@ -71,6 +73,13 @@ _SIGS = {
     "tct_backproject": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, _P, _P]),
     "tct_trace": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),
     "tct_trace_rays": (C.c_int, [_P, _P, _P, _P, _P, C.c_int32, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),
+    "tct_dot": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
+    "tct_axpy_ratio": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.c_double, _P]),
+    "tct_xpay_ratio": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P]),
+    "tct_axpby": (C.c_int, [_P, _P, C.c_int64, C.c_float, C.c_float, _P]),
+    "tct_mul": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "tct_recip": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P]),
+    "tct_copy_f64": (C.c_int, [_P, _P, C.c_int32, _P]),
     "tct_last_error": (C.c_char_p, []),
     "tct_version": (C.c_char_p, []),
 }

@@ -249,16 +249,12 @@ tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* pr
   DeviceGuard dg(m->device);
   if (mode == TCT_BP_GATHER)
     return backproject_gather(m, g, proj, xhat, accumulate, entry, default_tile_u(), (hipStream_t)s);
-  if (mode != TCT_BP_ATOMIC) {
+  if (mode != TCT_BP_ATOMIC && mode != TCT_BP_ATOMIC_DIRECT) {
     set_error("tct_backproject: unknown mode");
     return TCT_E_ARG;
   }
-  if (!accumulate) {
-    st = launch_fill(xhat, m->nt, 0.f, (hipStream_t)s);
-    if (st != TCT_OK) return st;
-  }
-  return launch_pixel_walk(kModeBackAtomic, m, g, 0, g->na, entry, proj, xhat, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, default_tile_u(), (hipStream_t)s);
+  return backproject_atomic(m, g, proj, xhat, accumulate, entry, default_tile_u(), mode == TCT_BP_ATOMIC,
+                            (hipStream_t)s);
 }
 
 namespace {
@@ -327,6 +323,63 @@ tct_status tct_trace_rays(const tct_mesh* m, const float* S, const float* P, con
   }
   DeviceGuard dg(m->device);
   return trace_common(m, nullptr, nullptr, S, P, U, V, n, offsets, tets, lengths, cap, needed, (hipStream_t)s);
+}
+
+tct_status tct_dot(const float* a, const float* b, int64_t n, double* result, double* workspace, tct_stream s) {
+  if (!a || !b || !result || !workspace || n < 0) {
+    set_error("tct_dot: bad arguments");
+    return TCT_E_ARG;
+  }
+  return blas_dot(a, b, n, result, workspace, (hipStream_t)s);
+}
+
+tct_status tct_axpy_ratio(float* y, const float* x, int64_t n, const double* num, const double* den, double sign,
+                          tct_stream s) {
+  if (!y || !x || !num || !den || n < 0) {
+    set_error("tct_axpy_ratio: bad arguments");
+    return TCT_E_ARG;
+  }
+  return blas_axpy_ratio(y, x, n, num, den, sign, (hipStream_t)s);
+}
+
+tct_status tct_xpay_ratio(float* p, const float* x, int64_t n, const double* num, const double* den, tct_stream s) {
+  if (!p || !x || !num || !den || n < 0) {
+    set_error("tct_xpay_ratio: bad arguments");
+    return TCT_E_ARG;
+  }
+  return blas_xpay_ratio(p, x, n, num, den, (hipStream_t)s);
+}
+
+tct_status tct_axpby(float* y, const float* x, int64_t n, float a, float b, tct_stream s) {
+  if (!y || !x || n < 0) {
+    set_error("tct_axpby: bad arguments");
+    return TCT_E_ARG;
+  }
+  return blas_axpby(y, x, n, a, b, (hipStream_t)s);
+}
+
+tct_status tct_mul(float* y, const float* a, const float* b, int64_t n, tct_stream s) {
+  if (!y || !a || !b || n < 0) {
+    set_error("tct_mul: bad arguments");
+    return TCT_E_ARG;
+  }
+  return blas_mul(y, a, b, n, (hipStream_t)s);
+}
+
+tct_status tct_recip(float* y, const float* a, int64_t n, float eps, tct_stream s) {
+  if (!y || !a || n < 0) {
+    set_error("tct_recip: bad arguments");
+    return TCT_E_ARG;
+  }
+  return blas_recip(y, a, n, eps, (hipStream_t)s);
+}
+
+tct_status tct_copy_f64(double* dst, const double* src, int32_t n, tct_stream s) {
+  if (!dst || !src || n < 0) {
+    set_error("tct_copy_f64: bad arguments");
+    return TCT_E_ARG;
+  }
+  return blas_copy_f64(dst, src, n, (hipStream_t)s);
 }
 
 }  // extern "C"

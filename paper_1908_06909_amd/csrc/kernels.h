@@ -18,7 +18,10 @@ enum WalkMode {
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
                              const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
                              int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
-                             hipStream_t s);
+                             hipStream_t s, int lds_table = 0);
+
+tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
+                              const int32_t* entry, int tile_u, int lds_table, hipStream_t s);
 
 tct_status launch_list_walk(int mode, const tct_mesh* m, const tct_geom* g, const int64_t* ids, const float* S,
                             const float* P, const float* U, const float* V, int32_t n, int64_t* counts,
@@ -40,5 +43,14 @@ tct_status geom_build(const tct_cone* cone, const double* angles, int32_t na, in
 tct_status check_geometry(const tct_mesh* m, const tct_geom* g);
 
 int default_tile_u();
+
+tct_status blas_dot(const float* a, const float* b, int64_t n, double* result, double* workspace, hipStream_t s);
+tct_status blas_axpy_ratio(float* y, const float* x, int64_t n, const double* num, const double* den, double sign,
+                           hipStream_t s);
+tct_status blas_xpay_ratio(float* p, const float* x, int64_t n, const double* num, const double* den, hipStream_t s);
+tct_status blas_axpby(float* y, const float* x, int64_t n, float a, float b, hipStream_t s);
+tct_status blas_mul(float* y, const float* a, const float* b, int64_t n, hipStream_t s);
+tct_status blas_recip(float* y, const float* a, int64_t n, float eps, hipStream_t s);
+tct_status blas_copy_f64(double* dst, const double* src, int n, hipStream_t s);
 
 }  // namespace tct

@@ -50,6 +50,7 @@ struct Ray {
   float3 ad;  // |d|
   float3 M;   // fl(S + d / 2): reference point near the mesh for ray parameters
   float dn;   // |d| (Euclidean)
+  float dd;   // |d|^2
 };
 
 struct LaneStats {
@@ -68,7 +69,8 @@ __device__ __forceinline__ void finish_ray(Ray& r) {
   r.d = f3sub(r.P, r.S);
   r.ad = f3abs(r.d);
   r.M = make_float3(r.S.x + 0.5f * r.d.x, r.S.y + 0.5f * r.d.y, r.S.z + 0.5f * r.d.z);
-  r.dn = sqrtf(r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z);
+  r.dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
+  r.dn = sqrtf(r.dd);
 }
 
 // Pixel ray: P = fl(fl(D + fl(u U)) + fl(v V)) per component, no contraction.
@@ -95,6 +97,25 @@ __device__ __noinline__ int slow_edge_sign(float3 S, float3 P, float3 U, float3 
   int sg = perturbed_edge_sign(s, pp, u, v, a, b, &flags);
   return (sg + 1) | (int)(flags << 2);
 }
+
+// Ray parameter s = t - 1/2 where S + t (P - S) meets the plane through
+// `on` with normal (a - on) x (b - on), in float64 from the exact float32
+// inputs.  Used when the crossing is ill-conditioned (the face is nearly
+// parallel to the ray), where float32 rounding of any point on the ray is
+// amplified by 1 / cos(angle between ray and normal).
+__device__ __noinline__ double crossing_s_fp64(float3 S, float3 P, float3 on, float3 a, float3 b) {
+  double dx = (double)P.x - S.x, dy = (double)P.y - S.y, dz = (double)P.z - S.z;
+  double ax = (double)a.x - on.x, ay = (double)a.y - on.y, az = (double)a.z - on.z;
+  double bx = (double)b.x - on.x, by = (double)b.y - on.y, bz = (double)b.z - on.z;
+  double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+  double ox = (double)on.x - S.x, oy = (double)on.y - S.y, oz = (double)on.z - S.z;
+  return (ox * nx + oy * ny + oz * nz) / (dx * nx + dy * ny + dz * nz) - 0.5;
+}
+
+// cos^2 of the angle between the ray and a face normal below which the
+// crossing is recomputed in float64: the float32 error of a crossing is about
+// 2^-23 |Q| / cos, so 1/8 keeps it near 1e-6 of the chord.
+constexpr float kGrazingCos2 = 1.0f / 64.0f;
 
 __device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, LaneStats& st) {
   if (fast != 2) return fast;
@@ -199,6 +220,32 @@ __device__ __forceinline__ unsigned remap_local(unsigned p, unsigned f, unsigned
   return rank + (rank >= back ? 1u : 0u);
 }
 
+// Per-block accumulation table for the backprojection.  Neighbouring rays
+// of a pixel block cross mostly the same tetrahedra (at the benchmark pitch a
+// 16 x 16 block spans about two elements), so scattering every segment with a
+// global atomic makes dozens of lanes update one address at once.  Instead
+// each block sums its segments per tetrahedron in an LDS open-addressing
+// table (key = tetrahedron, linear probing) and flushes one global atomic per
+// distinct tetrahedron at the end; a segment that finds no slot within
+// kLdsProbes probes goes straight to global memory.
+constexpr int kLdsSlots = 2048;
+constexpr int kLdsProbes = 8;
+
+__device__ __forceinline__ void lds_accumulate(int* keys, float* vals, int tet, float v, float* xhat) {
+  unsigned h = ((unsigned)tet * 2654435761u) >> 21;  // 11-bit multiplicative hash
+#pragma unroll 1
+  for (int p = 0; p < kLdsProbes; ++p) {
+    unsigned slot = (h + p) & (kLdsSlots - 1);
+    int k = keys[slot];
+    if (k == -1) k = atomicCAS(keys + slot, -1, tet);
+    if (k == -1 || k == tet) {
+      atomicAdd(vals + slot, v);
+      return;
+    }
+  }
+  unsafeAtomicAdd(xhat + tet, v);
+}
+
 template <int MODE>
 struct WalkOut {
   // FWD
@@ -207,6 +254,8 @@ struct WalkOut {
   // BWD / GATHER_FILL: weight = y_j * |d|
   float weight = 0.f;
   float* xhat = nullptr;
+  int* lds_keys = nullptr;  // per-block accumulation table (BWD), null = direct atomics
+  float* lds_vals = nullptr;
   // TRACE / GATHER_FILL output cursor
   int32_t* out_tet = nullptr;
   float* out_len = nullptr;
@@ -236,12 +285,8 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
   // (v - Q) . n stays proportional to the element size rather than to the
   // source distance.  Only segment lengths are accumulated, never
   // differences of rounded parameters.
-  float s_in;
-  {
-    float3 n = f3cross(f3sub(a1, a0), f3sub(a2, a0));
-    s_in = f3dot(f3sub(a0, r.M), n) / f3dot(r.d, n);
-    s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
-  }
+  float s_in = (float)crossing_s_fp64(r.S, r.P, a0, a1, a2);
+  s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
   float xcur = 0.f;
   if constexpr (MODE == kModeForward) xcur = o.x[tet];
   const int cap = M.nt + 1;
@@ -278,8 +323,16 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
       break;
     }
     float3 n = f3cross(ei, ej);
-    float3 Q = make_float3(r.M.x + s_in * r.d.x, r.M.y + s_in * r.d.y, r.M.z + s_in * r.d.z);
-    float dt = f3dot(f3sub(v, Q), n) / f3dot(r.d, n);
+    float den = f3dot(r.d, n);
+    float dt;
+    if (den * den >= kGrazingCos2 * r.dd * f3dot(n, n)) {
+      float3 Q = make_float3(r.M.x + s_in * r.d.x, r.M.y + s_in * r.d.y, r.M.z + s_in * r.d.z);
+      dt = f3dot(f3sub(v, Q), n) / den;
+    } else {
+      float3 ai = k == 2 ? a0 : (k == 0 ? a1 : a2);
+      float3 aj = k == 2 ? a1 : (k == 0 ? a2 : a0);
+      dt = (float)(crossing_s_fp64(r.S, r.P, v, ai, aj) - (double)s_in);
+    }
     dt = fminf(fmaxf(dt, 0.0f), fmaxf(0.5f - s_in, 0.0f));
     st.steps++;
     if (dt == 0.f) st.zero++;
@@ -289,7 +342,12 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
     if constexpr (MODE == kModeForward) {
       o.acc += (double)dt * (double)xcur;
     } else if constexpr (MODE == kModeBackAtomic) {
-      if (dt > 0.f) unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
+      if (dt > 0.f) {
+        if (o.lds_keys)
+          lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.xhat);
+        else
+          unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
+      }
     } else if constexpr (MODE == kModeCountAll) {
       o.count++;
     } else if constexpr (MODE == kModeCountPos) {
@@ -348,20 +406,22 @@ __device__ __forceinline__ void flush_stats(const MeshView& M, LaneStats& st, in
   }
 }
 
+// Pixel blocks: a 256-thread block covers 16 x 16 pixels of one angle, as
+// four 8 x 8 wavefronts arranged 2 x 2.
 struct TileMap {
-  int tile_u, tile_v, ntu, ntv;
+  int nbu, nbv;  // blocks along u and v
 };
 
-// Map (wave, lane) to a pixel ray; returns false for lanes off the detector.
-__device__ __forceinline__ bool tile_ray(const GeomView& g, const TileMap& tm, int64_t wave, int lane, int a0,
+__device__ __forceinline__ bool tile_ray(const GeomView& g, const TileMap& tm, int64_t block, int tid, int a0,
                                          int na_chunk, int* a, int* i, int* j) {
-  int64_t per_angle = (int64_t)tm.ntu * tm.ntv;
-  int64_t aa = wave / per_angle;
-  int64_t rem = wave - aa * per_angle;
-  int tv = (int)(rem / tm.ntu), tu = (int)(rem - (int64_t)tv * tm.ntu);
+  int64_t per_angle = (int64_t)tm.nbu * tm.nbv;
+  int64_t aa = block / per_angle;
+  int64_t rem = block - aa * per_angle;
+  int bv = (int)(rem / tm.nbu), bu = (int)(rem - (int64_t)bv * tm.nbu);
+  int wave = tid >> 6, lane = tid & 63;
   *a = a0 + (int)aa;
-  *i = tu * tm.tile_u + lane % tm.tile_u;
-  *j = tv * tm.tile_v + lane / tm.tile_u;
+  *i = bu * 16 + (wave & 1) * 8 + (lane & 7);
+  *j = bv * 16 + (wave >> 1) * 8 + (lane >> 3);
   return aa < na_chunk && *i < g.nu && *j < g.nv;
 }
 
@@ -379,13 +439,39 @@ template <int MODE>
 __global__ __launch_bounds__(256) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
                                                          const int32_t* entry, const float* in, float* out_f32,
                                                          int32_t* out_i32, int64_t* counts, const int64_t* offsets,
-                                                         int32_t* keys, float* vals) {
-  int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
+                                                         int32_t* keys, float* vals, int lds_table) {
   int a, i, j;
-  bool active = tile_ray(G, tm, wave, lane, a0, na_chunk, &a, &i, &j);
+  bool active = tile_ray(G, tm, blockIdx.x, threadIdx.x, a0, na_chunk, &a, &i, &j);
   LaneStats st;
-  if (active) {
+  if constexpr (MODE == kModeBackAtomic) {
+    __shared__ int tkeys[kLdsSlots];
+    __shared__ float tvals[kLdsSlots];
+    if (lds_table) {
+      for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
+        tkeys[k] = -1;
+        tvals[k] = 0.f;
+      }
+      __syncthreads();
+    }
+    if (active) {
+      int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
+      Ray r = cone_ray(G, a, i, j);
+      int e = entry ? entry[rid] : find_entry(M, r, st);
+      WalkOut<MODE> o;
+      o.xhat = out_f32;
+      if (lds_table) {
+        o.lds_keys = tkeys;
+        o.lds_vals = tvals;
+      }
+      o.weight = in[rid] * r.dn;
+      if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, e, o, st);
+    }
+    if (lds_table) {
+      __syncthreads();
+      for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x)
+        if (tkeys[k] >= 0) unsafeAtomicAdd(out_f32 + tkeys[k], tvals[k]);
+    }
+  } else if (active) {
     int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
     int64_t rid0 = (int64_t)a0 * G.nv * G.nu;
     Ray r = cone_ray(G, a, i, j);
@@ -397,11 +483,6 @@ __global__ __launch_bounds__(256) void pixel_walk_kernel(MeshView M, GeomView G,
       o.x = in;
       if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
       out_f32[rid] = (float)(o.acc * (double)r.dn);
-    } else if constexpr (MODE == kModeBackAtomic) {
-      WalkOut<MODE> o;
-      o.xhat = out_f32;
-      o.weight = in[rid] * r.dn;
-      if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, e, o, st);
     } else if constexpr (MODE == kModeCountPos) {
       WalkOut<MODE> o;
       if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
@@ -477,55 +558,52 @@ __global__ void permute_kernel(const float* in, float* out, const int32_t* perm,
 
 // ---------------------------------------------------------------- launchers
 
-static TileMap make_tiles(const GeomView& g, int tile_u) {
+static TileMap make_tiles(const GeomView& g) {
   TileMap t;
-  t.tile_u = tile_u;
-  t.tile_v = 64 / tile_u;
-  t.ntu = (g.nu + t.tile_u - 1) / t.tile_u;
-  t.ntv = (g.nv + t.tile_v - 1) / t.tile_v;
+  t.nbu = (g.nu + 15) / 16;
+  t.nbv = (g.nv + 15) / 16;
   return t;
 }
 
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
                              const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
                              int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
-                             hipStream_t s) {
+                             hipStream_t s, int lds_table) {
+  (void)tile_u;
   MeshView M = m->view();
   GeomView G = g->view();
-  TileMap tm = make_tiles(G, tile_u);
-  int64_t waves = (int64_t)tm.ntu * tm.ntv * na_chunk;
-  int64_t blocks = (waves + 3) / 4;
+  TileMap tm = make_tiles(G);
+  int64_t blocks = (int64_t)tm.nbu * tm.nbv * na_chunk;
   if (blocks <= 0) return TCT_OK;
   if (blocks > 0x7fffffff) {
     set_error("too many rays in one launch");
     return TCT_E_ARG;
   }
   dim3 grid((unsigned)blocks), block(256);
+#define TCT_LAUNCH(MODE_)                                                                                        \
+  hipLaunchKernelGGL(pixel_walk_kernel<MODE_>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in, out_f32, \
+                     out_i32, counts, offsets, keys, vals, lds_table)
   switch (mode) {
     case kModeEntry:
-      hipLaunchKernelGGL(pixel_walk_kernel<kModeEntry>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
-                         out_f32, out_i32, counts, offsets, keys, vals);
+      TCT_LAUNCH(kModeEntry);
       break;
     case kModeForward:
-      hipLaunchKernelGGL(pixel_walk_kernel<kModeForward>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
-                         out_f32, out_i32, counts, offsets, keys, vals);
+      TCT_LAUNCH(kModeForward);
       break;
     case kModeBackAtomic:
-      hipLaunchKernelGGL(pixel_walk_kernel<kModeBackAtomic>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
-                         out_f32, out_i32, counts, offsets, keys, vals);
+      TCT_LAUNCH(kModeBackAtomic);
       break;
     case kModeCountPos:
-      hipLaunchKernelGGL(pixel_walk_kernel<kModeCountPos>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
-                         out_f32, out_i32, counts, offsets, keys, vals);
+      TCT_LAUNCH(kModeCountPos);
       break;
     case kModeGatherFill:
-      hipLaunchKernelGGL(pixel_walk_kernel<kModeGatherFill>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in,
-                         out_f32, out_i32, counts, offsets, keys, vals);
+      TCT_LAUNCH(kModeGatherFill);
       break;
     default:
       set_error("bad walk mode");
       return TCT_E_ARG;
   }
+#undef TCT_LAUNCH
   TCT_HIP(hipGetLastError());
   return TCT_OK;
 }
@@ -553,6 +631,16 @@ tct_status launch_fill(float* p, int64_t n, float v, hipStream_t s) {
   hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   TCT_HIP(hipGetLastError());
   return TCT_OK;
+}
+
+tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
+                              const int32_t* entry, int tile_u, int lds_table, hipStream_t s) {
+  if (!accumulate) {
+    tct_status st = launch_fill(xhat, m->nt, 0.f, s);
+    if (st != TCT_OK) return st;
+  }
+  return launch_pixel_walk(kModeBackAtomic, m, g, 0, g->na, entry, proj, xhat, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, tile_u, s, lds_table);
 }
 
 tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s) {

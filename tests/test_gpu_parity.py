@@ -1,10 +1,18 @@
 """GPU parity: the HIP walk (through the C ABI) against the CPU oracle.
 
-Bars (float32 path vs float64 oracle):
+Bars (float32 path vs float64 oracle), with chord_j the ray's length inside
+the mesh and |d_j| its full length |P - S|:
   * traversed-tetrahedron sequences, zero-length passages included: identical;
-  * segment lengths: |L_gpu - L_ref| <= 1e-5 * chord of the ray;
-  * projections: |b_gpu - b_ref| <= 1e-5 * sum_i a_ij |x_i|; misses exactly 0;
-  * backprojections: |dxhat_i| <= 1e-5 * sum_{j: a_ij>0} chord_j |y_j|
+  * segment lengths: |L_gpu - L_ref| <= 1e-5 * max(chord_j, |d_j| / 64).
+    The floor: the kernels keep ray parameters as float32 numbers in
+    [-1/2, 1/2], whose rounding moves a crossing by up to ~2^-25 |d_j|, up to
+    8x more for crossings just above the float64 grazing threshold; 1e-5/64
+    = 2^-22.6 covers a few such errors.  It matters only for rays that clip
+    the hull with a chord shorter than |d_j| / 64;
+  * projections: |b_gpu - b_ref| <= 1e-5 * sum_i a_ij |x_i|
+    + 1e-5 (|d_j| / 64) TV_j(x), TV_j = sum over the ray's crossings of the
+    jump of x (length errors telescope); misses exactly 0;
+  * backprojections: |dxhat_i| <= 1e-5 * sum_{j: a_ij>0} max(chord_j, |d_j|/64) |y_j|
     + n_i 2^-24 (A^T|y|)_i (n_i = terms summed into element i, float32
     accumulation), and l2-relative <= 1e-5;
   * adjoint: |<Ax,y> - <x,A^T y>| <= 1e-5 <|A||x|, |y|>.
@@ -74,12 +82,42 @@ def case(name):
     return _cases[name]
 
 
-def compare_traces(gpu, ref):
+def ray_lengths(c, ids):
+    S, P, _, _ = c.orc.rays(ids)
+    return np.linalg.norm(P.astype(np.float64) - S, axis=1)
+
+
+def compare_traces(gpu, ref, dlen):
     assert len(gpu) == len(ref)
     for k, ((gt, gl), (rt, rl)) in enumerate(zip(gpu, ref)):
         assert np.array_equal(gt, rt), f"ray {k}: sequences differ\n gpu {gt[:40]}\n ref {rt[:40]}"
         chord = float(rl.sum())
-        assert np.all(np.abs(gl.astype(np.float64) - rl) <= 1e-5 * max(chord, 1e-30)), f"ray {k}: lengths"
+        err = np.abs(gl.astype(np.float64) - rl)
+        i = int(np.argmax(err)) if len(err) else 0
+        assert np.all(err <= 1e-5 * max(chord, dlen[k] / 64)), (
+            f"ray {k}: lengths; chord {chord:.6e} n {len(rl)} worst seg {i} gpu {gl[i]:.9e} ref {rl[i]:.9e} "
+            f"err {err[i]:.3e}; all gpu {gl[:8]} ref {rl[:8]}")
+
+
+def forward_tolerance(c, x, ids=None):
+    """1e-5 sum_i a_ij |x_i| + 1e-5 (|d_j|/64) TV_j(x) per listed ray."""
+    ids = np.arange(c.orc.nrays) if ids is None else np.asarray(ids)
+    absb = c.orc.forward(np.abs(x), ids)
+    tv = np.zeros(len(ids))
+    for k, (tt, _) in enumerate(c.orc.trace(ids)):
+        if len(tt):
+            xs = np.concatenate([[0.0], x[tt].astype(np.float64), [0.0]])
+            tv[k] = np.abs(np.diff(xs)).sum()
+    return 1e-5 * absb + 1e-5 * ray_lengths(c, ids) / 64 * tv + 1e-30
+
+
+def assert_within(got, ref, tol, what):
+    err = np.abs(np.asarray(got, np.float64) - ref)
+    bad = err > tol
+    if bad.any():
+        k = int(np.argmax(err / np.maximum(tol, 1e-300)))
+        raise AssertionError(f"{what}: {int(bad.sum())} of {bad.size} out of tolerance; worst index {k}: "
+                             f"got {got[k]!r} ref {ref[k]!r} err {err[k]:.3e} tol {tol[k]:.3e}")
 
 
 def check_stats(mesh):
@@ -92,7 +130,7 @@ def check_stats(mesh):
 def test_cfg0_all_sequences_bitexact():
     c = case("cfg0")
     ids = np.arange(c.orc.nrays)
-    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    compare_traces(c.P.trace(ids), c.orc.trace(ids), ray_lengths(c, ids))
     check_stats(c.mesh)
 
 
@@ -104,8 +142,8 @@ def test_cfg0_forward():
     got = c.P.forward(xi).cpu().numpy().ravel()
     got_nc = c.P.forward(xi, use_cache=False).cpu().numpy().ravel()
     assert np.array_equal(got, got_nc), "entry cache changes the result"
-    tol = 1e-5 * c.orc.forward(np.abs(x))
-    assert np.all(np.abs(got - ref) <= tol + 1e-30)
+    tol = forward_tolerance(c, x)
+    assert_within(got, ref, tol, "cfg0 forward")
     assert np.all(got[ref == 0] == 0)
     check_stats(c.mesh)
 
@@ -117,15 +155,16 @@ def _bp_tolerance(c, y):
     nt = c.orc.nt
     chord_w = np.zeros(nt)
     nterm = np.zeros(nt)
+    dlen = ray_lengths(c, ids)
     for j, (tt, ll) in enumerate(tr):
         pos = ll > 0
-        np.add.at(chord_w, tt[pos], ll.sum() * abs(float(y[j])))
+        np.add.at(chord_w, tt[pos], max(ll.sum(), dlen[j] / 64) * abs(float(y[j])))
         np.add.at(nterm, tt[pos], 1)
     absbp = c.orc.backproject(np.abs(y))
     return 1e-5 * chord_w + nterm * 2.0 ** -24 * absbp + 1e-30
 
 
-@pytest.mark.parametrize("mode", ["atomic", "gather"])
+@pytest.mark.parametrize("mode", ["atomic", "atomic_direct", "gather"])
 def test_cfg0_backproject(mode):
     c = case("cfg0")
     rng = np.random.default_rng(31)
@@ -134,8 +173,7 @@ def test_cfg0_backproject(mode):
     yt = torch.as_tensor(y, device=DEV)
     got = c.to_user(c.P.backproject(yt, mode=mode)).astype(np.float64)
     tol = _bp_tolerance(c, y)
-    bad = np.abs(got - ref) > tol
-    assert not bad.any(), f"{bad.sum()} elements out of tolerance; worst {np.max(np.abs(got-ref)/tol)}"
+    assert_within(got, ref, tol, f"cfg0 backprojection {mode}")
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
     check_stats(c.mesh)
 
@@ -161,7 +199,7 @@ def test_cfg0_adjoint():
     y = rng.uniform(-1, 1, c.orc.nrays).astype(f32)
     xi = c.x_internal(x)
     Ax = c.P.forward(xi).cpu().numpy().ravel().astype(np.float64)
-    for mode in ("atomic", "gather"):
+    for mode in ("atomic", "atomic_direct", "gather"):
         Aty = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode)).astype(np.float64)
         lhs = float(np.dot(Ax, y))
         rhs = float(np.dot(x.astype(np.float64), Aty))
@@ -215,7 +253,8 @@ def test_degenerate_custom_rays_match_oracle():
     om = oracle.OracleMesh(verts, tets)
     rays = _degenerate_rays()
     S, P, U, V = (np.array([r[k] for r in rays], f32) for k in range(4))
-    compare_traces(tct.trace_rays(m, S, P, U, V), oracle.oracle.trace_rays(om, S, P, U, V))
+    compare_traces(tct.trace_rays(m, S, P, U, V), oracle.oracle.trace_rays(om, S, P, U, V),
+                   np.linalg.norm(P.astype(np.float64) - S, axis=1))
     st = check_stats(m)
     assert st["perturbed_ties"] > 0 and st["exact_stage"] > 0
 
@@ -239,11 +278,11 @@ def _degenerate_ids(nu, nv, na, stride_a=1):
 def test_graded_small_all_sequences():
     c = case("graded_small")
     ids = np.arange(c.orc.nrays)
-    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    compare_traces(c.P.trace(ids), c.orc.trace(ids), ray_lengths(c, ids))
     xi = c.x_internal(c.w.x)
     got = c.P.forward(xi).cpu().numpy().ravel()
     ref = c.orc.forward(c.w.x)
-    assert np.all(np.abs(got - ref) <= 1e-5 * c.orc.forward(np.abs(c.w.x)) + 1e-30)
+    assert_within(got, ref, forward_tolerance(c, c.w.x), "graded forward")
     st = check_stats(c.mesh)
     assert st["perturbed_ties"] > 0
 
@@ -254,12 +293,11 @@ def test_cfg2_sampled_sequences_and_forward():
     rng = np.random.default_rng(2)
     ids = np.concatenate([_degenerate_ids(cone.nu, cone.nv, len(c.w.angles), stride_a=45),
                           rng.integers(0, c.orc.nrays, 1500)])
-    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    compare_traces(c.P.trace(ids), c.orc.trace(ids), ray_lengths(c, ids))
     xi = c.x_internal(c.w.x)
     full = c.P.forward(xi).cpu().numpy().ravel()
     ref = c.orc.forward(c.w.x, ids)
-    tol = 1e-5 * c.orc.forward(np.abs(c.w.x), ids)
-    assert np.all(np.abs(full[ids] - ref) <= tol + 1e-30)
+    assert_within(full[ids], ref, forward_tolerance(c, c.w.x, ids), "cfg2 forward")
     check_stats(c.mesh)
 
 
@@ -269,12 +307,11 @@ def test_cfg1_sampled_sequences_and_forward():
     rng = np.random.default_rng(1)
     n_per = c.w.cone.nu * c.w.cone.nv
     ids = np.concatenate([rng.integers(0, c.orc.nrays, 2500), 100 * n_per + 256 * 512 + np.arange(512)])
-    compare_traces(c.P.trace(ids[:800]), c.orc.trace(ids[:800]))
+    compare_traces(c.P.trace(ids[:800]), c.orc.trace(ids[:800]), ray_lengths(c, ids[:800]))
     xi = c.x_internal(c.w.x)
     full = c.P.forward(xi).cpu().numpy().ravel()
     ref = c.orc.forward(c.w.x, ids)
-    tol = 1e-5 * c.orc.forward(np.abs(c.w.x), ids)
-    assert np.all(np.abs(full[ids] - ref) <= tol + 1e-30)
+    assert_within(full[ids], ref, forward_tolerance(c, c.w.x, ids), "cfg1 forward")
     assert np.all(full != 0)  # every ray of this geometry hits the cube
     check_stats(c.mesh)
 
@@ -283,13 +320,13 @@ def test_cfg1_sampled_sequences_and_forward():
 def test_ragged_detector_and_missing_rays():
     c = case("ragged")
     ids = np.arange(c.orc.nrays)
-    compare_traces(c.P.trace(ids), c.orc.trace(ids))
+    compare_traces(c.P.trace(ids), c.orc.trace(ids), ray_lengths(c, ids))
     xi = c.x_internal(c.w.x)
     got = c.P.forward(xi).cpu().numpy().ravel()
     ref = c.orc.forward(c.w.x)
     assert (ref == 0).sum() > 0, "geometry should include rays that miss"
     assert np.all(got[ref == 0] == 0)
-    assert np.all(np.abs(got - ref) <= 1e-5 * c.orc.forward(np.abs(c.w.x)) + 1e-30)
+    assert_within(got, ref, forward_tolerance(c, c.w.x), "ragged forward")
     y = np.random.default_rng(3).uniform(0, 1, c.orc.nrays).astype(f32)
     bp = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode="gather"))
     assert np.linalg.norm(bp - c.orc.backproject(y)) <= 1e-5 * np.linalg.norm(c.orc.backproject(y))
