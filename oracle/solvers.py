@@ -1,0 +1,83 @@
+"""Float64 reference solvers on the oracle's explicit system matrix.
+
+TEST INFRASTRUCTURE ONLY.  The paper's operator A (Section II-A, Eq. 1:
+a_ij = length of ray j inside tetrahedron i) is assembled explicitly from the
+oracle's traced walks as a scipy sparse matrix, and the textbook algorithms
+the paper names as consumers of A and A^T (CGLS, SART-family SIRT) are
+written out plainly in float64.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def system_matrix(orc, ids=None) -> sp.csr_matrix:
+    """A restricted to the listed rays (all when None): rows = rays, columns = user tetrahedra."""
+    ids = np.arange(orc.nrays) if ids is None else np.asarray(ids, np.int64)
+    rows, cols, vals = [], [], []
+    for k, (tt, ll) in enumerate(orc.trace(ids)):
+        rows.append(np.full(len(tt), k, np.int64))
+        cols.append(tt.astype(np.int64))
+        vals.append(ll)
+    rows = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+    cols = np.concatenate(cols) if cols else np.zeros(0, np.int64)
+    vals = np.concatenate(vals) if vals else np.zeros(0)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(len(ids), orc.nt))
+
+
+def loss(A, x, b) -> float:
+    r = A @ x - b
+    return 0.5 * float(r @ r)
+
+
+def gradient(A, x, b) -> np.ndarray:
+    """Gradient of 0.5 ||A x - b||^2: A^T (A x - b)."""
+    return A.T @ (A @ x - b)
+
+
+def cgls(A, b, iters: int, x0=None):
+    """Conjugate gradients on A^T A x = A^T b (Hestenes-Stiefel form for least squares).
+
+    Returns (x, rr, xs) with rr[k] = ||b - A x_k||^2 for k = 0..iters and xs the iterates.
+    """
+    x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
+    r = b - A @ x
+    s = A.T @ r
+    p = s.copy()
+    gamma = float(s @ s)
+    rr = [float(r @ r)]
+    xs = [x.copy()]
+    for _ in range(iters):
+        q = A @ p
+        delta = float(q @ q)
+        alpha = gamma / delta if delta != 0 else 0.0
+        x = x + alpha * p
+        r = r - alpha * q
+        s = A.T @ r
+        gamma_new = float(s @ s)
+        beta = gamma_new / gamma if gamma != 0 else 0.0
+        p = s + beta * p
+        gamma = gamma_new
+        rr.append(float(r @ r))
+        xs.append(x.copy())
+    return x, np.array(rr), xs
+
+
+def sirt(A, b, iters: int, lam: float = 1.0, x0=None):
+    """x += lam * C A^T R (b - A x), R = diag(1 / row sums), C = diag(1 / column sums).
+
+    Returns (x, rr) with rr[k] = ||b - A x_k||^2 before iteration k.
+    """
+    row = np.asarray(A.sum(axis=1)).ravel()
+    col = np.asarray(A.sum(axis=0)).ravel()
+    R = np.where(row > 0, 1.0 / np.where(row > 0, row, 1.0), 0.0)
+    Cw = np.where(col > 0, 1.0 / np.where(col > 0, col, 1.0), 0.0)
+    x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
+    rr = []
+    for _ in range(iters):
+        r = b - A @ x
+        rr.append(float(r @ r))
+        x = x + lam * Cw * (A.T @ (R * r))
+    return x, np.array(rr)
