@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--gather", action="store_true")
     ap.add_argument("--json-extra", default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes (3 times) to calibrate HBM counters")
     return ap.parse_args()
 
 
@@ -84,6 +86,16 @@ def main():
                                    "and not launched", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 4 * n, "copies": 3}))
+        return
 
     import synth
     from paper_1908_06909_amd import ConeGeometry, Projector, TetMesh

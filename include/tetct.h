@@ -54,6 +54,7 @@ typedef void* tct_stream; /* hipStream_t */
 typedef struct tct_mesh tct_mesh;
 typedef struct tct_geom tct_geom;
 typedef struct tct_batch tct_batch;
+typedef struct tct_vecset tct_vecset;
 
 typedef enum {
   TCT_OK = 0,
@@ -180,6 +181,23 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
 tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
                            int accumulate, const int32_t* entry, tct_stream s);
 
+/* Launch options: the angles [a0, a0 + na) to process (projection arrays keep
+ * their full [na_total][nv][nu] layout; other angles are not touched) and the
+ * wavefront pixel tile width tile_u in {4, 8, 16, 32, 64} (tile height
+ * 64 / tile_u; a 256-thread block covers 2 x 2 tiles).  The paper tuned its
+ * pixel block shape per GPU and recommends re-tuning elsewhere (Section II-F). */
+typedef struct {
+  int32_t a0, na;
+  int32_t tile_u;
+} tct_range;
+
+/* tct_forward / tct_backproject restricted to an angle range with a tile shape
+ * (subset iterations such as OS-SART, and tile autotuning). */
+tct_status tct_forward_range(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
+                             const tct_range* r, tct_stream s);
+tct_status tct_backproject_range(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
+                                 int accumulate, const int32_t* entry, const tct_range* r, tct_stream s);
+
 /* Visited tetrahedra of selected rays, zero-length passages included, in CSR form.
  *   ray_ids  device int64 [nrays]
  *   offsets  device int64 [nrays + 1]   written: ray k owns [offsets[k], offsets[k+1])
@@ -228,6 +246,49 @@ tct_status tct_recip(float* y, const float* a, int64_t n, float eps, tct_stream 
 
 /* dst[0..n) = src[0..n) for device doubles (solver scalars). */
 tct_status tct_copy_f64(double* dst, const double* src, int32_t n, tct_stream s);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent problems (each its own mesh and geometry) processed by one
+ * persistent launch that pulls pixel blocks of every problem from a device
+ * work counter, most expensive problems first.  Vector arguments are
+ * "vector sets": tables of device pointers built once, so a batched call
+ * takes no host data and can be captured in a graph. */
+
+/* n device float arrays (ptrs[k] of lens[k] elements) on `device`.  The
+ * table is copied; the arrays stay caller-owned and must outlive the set. */
+tct_status tct_vecset_create(int32_t n, float* const* ptrs, const int64_t* lens, int device, tct_vecset** out);
+void tct_vecset_destroy(tct_vecset* v);
+
+#define TCT_VECSET_DOT_WORKSPACE 256 /* doubles of workspace per vector for tct_vecset_dot */
+
+/* results[k] (device double [n]) = a_k . b_k, float64, fixed order (reproducible).
+ * workspace: device double [n * TCT_VECSET_DOT_WORKSPACE]. */
+tct_status tct_vecset_dot(const tct_vecset* a, const tct_vecset* b, double* results, double* workspace,
+                          tct_stream s);
+/* y_k += sign * (num[k] / den[k]) * x_k   (num, den: device double [n]) */
+tct_status tct_vecset_axpy_ratio(const tct_vecset* y, const tct_vecset* x, const double* num, const double* den,
+                                 double sign, tct_stream s);
+/* p_k = x_k + (num[k] / den[k]) * p_k */
+tct_status tct_vecset_xpay_ratio(const tct_vecset* p, const tct_vecset* x, const double* num, const double* den,
+                                 tct_stream s);
+/* y_k[:] = value */
+tct_status tct_vecset_fill(const tct_vecset* y, float value, tct_stream s);
+
+/* A batch of n (mesh, geometry) problems on one device.  tile_u: host int32 [n]
+ * wavefront tile widths (NULL = 8).  entries: host array of n device entry
+ * caches from tct_entry (NULL, or NULL elements, = search in-kernel).  The
+ * handles must outlive the batch.  A batch is stream-exclusive: its work
+ * counter is reset by each call. */
+tct_status tct_batch_create(const tct_mesh* const* meshes, const tct_geom* const* geoms, int32_t n,
+                            const int32_t* tile_u, int32_t* const* entries, tct_batch** out);
+/* proj_k = A_k x_k for every problem (x: nt_k floats, internal order; proj: rays_k floats). */
+tct_status tct_batch_forward(tct_batch* b, const tct_vecset* x, const tct_vecset* proj, tct_stream s);
+/* xhat_k (+)= A_k^T proj_k for every problem (atomic mode with on-chip pre-summing). */
+tct_status tct_batch_backproject(tct_batch* b, const tct_vecset* proj, const tct_vecset* xhat, int accumulate,
+                                 tct_stream s);
+/* Total pixel blocks (queue items) of the batch. */
+int64_t tct_batch_items(const tct_batch* b);
+void tct_batch_destroy(tct_batch* b);
 
 /* ---------------------------------------------------------------- misc */
 

@@ -13,3 +13,8 @@ __all__ = ["TetMesh", "ConeGeometry", "Projector", "trace_rays"]
 from .solvers import CGLS, TetProject, cgls, project, sirt  # noqa: E402
 
 __all__ += ["TetProject", "project", "CGLS", "cgls", "sirt"]
+
+from .batch import BatchCGLS, BatchProjector, PlainCGLS, SetOps, VecSet  # noqa: E402
+from . import autotune  # noqa: E402
+
+__all__ += ["VecSet", "SetOps", "BatchProjector", "BatchCGLS", "PlainCGLS", "autotune"]

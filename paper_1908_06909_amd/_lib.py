@@ -32,6 +32,7 @@ TCT_BP_ATOMIC = 0
 TCT_BP_GATHER = 1
 TCT_BP_ATOMIC_DIRECT = 2
 TCT_DOT_WORKSPACE = 512
+TCT_VECSET_DOT_WORKSPACE = 256
 
 
 class TctError(RuntimeError):
@@ -43,6 +44,10 @@ class TctError(RuntimeError):
 class tct_cone(C.Structure):
     _fields_ = [("dso", C.c_double), ("dsd", C.c_double), ("nu", C.c_int32), ("nv", C.c_int32),
                 ("du", C.c_double), ("dv", C.c_double), ("off_u", C.c_double), ("off_v", C.c_double)]
+
+
+class tct_range(C.Structure):
+    _fields_ = [("a0", C.c_int32), ("na", C.c_int32), ("tile_u", C.c_int32)]
 
 
 class tct_stats(C.Structure):
@@ -80,6 +85,19 @@ _SIGS = {
     "tct_mul": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
     "tct_recip": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P]),
     "tct_copy_f64": (C.c_int, [_P, _P, C.c_int32, _P]),
+    "tct_forward_range": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "tct_backproject_range": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, _P, _P, _P]),
+    "tct_vecset_create": (C.c_int, [C.c_int32, _P, _P, C.c_int, C.POINTER(_P)]),
+    "tct_vecset_destroy": (None, [_P]),
+    "tct_vecset_dot": (C.c_int, [_P, _P, _P, _P, _P]),
+    "tct_vecset_axpy_ratio": (C.c_int, [_P, _P, _P, _P, C.c_double, _P]),
+    "tct_vecset_xpay_ratio": (C.c_int, [_P, _P, _P, _P, _P]),
+    "tct_vecset_fill": (C.c_int, [_P, C.c_float, _P]),
+    "tct_batch_create": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.POINTER(_P)]),
+    "tct_batch_forward": (C.c_int, [_P, _P, _P, _P]),
+    "tct_batch_backproject": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+    "tct_batch_items": (C.c_int64, [_P]),
+    "tct_batch_destroy": (None, [_P]),
     "tct_last_error": (C.c_char_p, []),
     "tct_version": (C.c_char_p, []),
 }

@@ -92,6 +92,77 @@ __global__ void copy_f64_kernel(double* dst, const double* src, int n) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// ---- vector sets: one launch over n vectors; block (p, c) handles chunk c of vector p.
+constexpr int kSetChunks = TCT_VECSET_DOT_WORKSPACE;
+
+__device__ __forceinline__ void chunk_range(int64_t len, int c, int64_t* b, int64_t* e) {
+  *b = len * c / kSetChunks;
+  *e = len * (c + 1) / kSetChunks;
+}
+
+__global__ __launch_bounds__(kDotThreads) void vs_dot_partial_kernel(float* const* A, float* const* B,
+                                                                     const int64_t* lens, double* ws) {
+  __shared__ double sh[kDotThreads];
+  int p = blockIdx.y, c = blockIdx.x;
+  int64_t b, e;
+  chunk_range(lens[p], c, &b, &e);
+  const float* a = A[p];
+  const float* bb = B[p];
+  double s = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += kDotThreads) s += (double)a[i] * (double)bb[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ws[(size_t)p * kSetChunks + c] = sh[0];
+}
+
+__global__ __launch_bounds__(kDotThreads) void vs_dot_final_kernel(const double* ws, double* results) {
+  __shared__ double sh[kDotThreads];
+  int p = blockIdx.x;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < kSetChunks; c += kDotThreads) s += ws[(size_t)p * kSetChunks + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) results[p] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void vs_axpy_ratio_kernel(float* const* Y, float* const* X, const int64_t* lens,
+                                                            const double* num, const double* den, double sign) {
+  int p = blockIdx.y, c = blockIdx.x;
+  int64_t b, e;
+  chunk_range(lens[p], c, &b, &e);
+  float a = (float)(sign * safe_ratio(num + p, den + p));
+  float* y = Y[p];
+  const float* x = X[p];
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) y[i] += a * x[i];
+}
+
+__global__ __launch_bounds__(256) void vs_xpay_ratio_kernel(float* const* Pp, float* const* X, const int64_t* lens,
+                                                            const double* num, const double* den) {
+  int p = blockIdx.y, c = blockIdx.x;
+  int64_t b, e;
+  chunk_range(lens[p], c, &b, &e);
+  float beta = (float)safe_ratio(num + p, den + p);
+  float* q = Pp[p];
+  const float* x = X[p];
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) q[i] = x[i] + beta * q[i];
+}
+
+__global__ __launch_bounds__(256) void vs_fill_kernel(float* const* Y, const int64_t* lens, float v) {
+  int p = blockIdx.y, c = blockIdx.x;
+  int64_t b, e;
+  chunk_range(lens[p], c, &b, &e);
+  float* y = Y[p];
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) y[i] = v;
+}
+
 }  // namespace
 
 tct_status blas_dot(const float* a, const float* b, int64_t n, double* result, double* workspace, hipStream_t s) {
@@ -142,6 +213,40 @@ tct_status blas_recip(float* y, const float* a, int64_t n, float eps, hipStream_
 tct_status blas_copy_f64(double* dst, const double* src, int n, hipStream_t s) {
   if (n <= 0) return TCT_OK;
   hipLaunchKernelGGL(copy_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, dst, src, n);
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+tct_status vecset_dot(const tct_vecset* a, const tct_vecset* b, double* results, double* workspace, hipStream_t s) {
+  if (a->n <= 0) return TCT_OK;
+  hipLaunchKernelGGL(vs_dot_partial_kernel, dim3(kSetChunks, a->n), dim3(kDotThreads), 0, s, a->d_ptrs, b->d_ptrs,
+                     a->d_lens, workspace);
+  hipLaunchKernelGGL(vs_dot_final_kernel, dim3(a->n), dim3(kDotThreads), 0, s, workspace, results);
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+tct_status vecset_axpy_ratio(const tct_vecset* y, const tct_vecset* x, const double* num, const double* den,
+                             double sign, hipStream_t s) {
+  if (y->n <= 0) return TCT_OK;
+  hipLaunchKernelGGL(vs_axpy_ratio_kernel, dim3(kSetChunks, y->n), dim3(256), 0, s, y->d_ptrs, x->d_ptrs, y->d_lens,
+                     num, den, sign);
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+tct_status vecset_xpay_ratio(const tct_vecset* p, const tct_vecset* x, const double* num, const double* den,
+                             hipStream_t s) {
+  if (p->n <= 0) return TCT_OK;
+  hipLaunchKernelGGL(vs_xpay_ratio_kernel, dim3(kSetChunks, p->n), dim3(256), 0, s, p->d_ptrs, x->d_ptrs, p->d_lens,
+                     num, den);
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
+}
+
+tct_status vecset_fill(const tct_vecset* y, float v, hipStream_t s) {
+  if (y->n <= 0) return TCT_OK;
+  hipLaunchKernelGGL(vs_fill_kernel, dim3(kSetChunks, y->n), dim3(256), 0, s, y->d_ptrs, y->d_lens, v);
   TCT_HIP(hipGetLastError());
   return TCT_OK;
 }

@@ -225,6 +225,58 @@ tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_s
                            nullptr, default_tile_u(), (hipStream_t)s);
 }
 
+namespace {
+tct_status check_range(const tct_geom* g, const tct_range* r) {
+  if (!r || r->a0 < 0 || r->na < 0 || r->a0 + r->na > g->na) {
+    set_error("tct_range: angles out of range");
+    return TCT_E_ARG;
+  }
+  if (r->tile_u != 4 && r->tile_u != 8 && r->tile_u != 16 && r->tile_u != 32 && r->tile_u != 64) {
+    set_error("tct_range: tile_u must be 4, 8, 16, 32 or 64");
+    return TCT_E_ARG;
+  }
+  return TCT_OK;
+}
+}  // namespace
+
+tct_status tct_forward_range(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
+                             const tct_range* r, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if ((st = check_range(g, r)) != TCT_OK) return st;
+  if (!x || !proj) {
+    set_error("tct_forward_range: null input or output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return launch_pixel_walk(kModeForward, m, g, r->a0, r->na, entry, x, proj, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, r->tile_u, (hipStream_t)s);
+}
+
+tct_status tct_backproject_range(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
+                                 int accumulate, const int32_t* entry, const tct_range* r, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if ((st = check_range(g, r)) != TCT_OK) return st;
+  if (!proj || !xhat) {
+    set_error("tct_backproject_range: null input or output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  if (mode == TCT_BP_GATHER)
+    return backproject_gather(m, g, proj, xhat, accumulate, entry, r->tile_u, r->a0, r->na, (hipStream_t)s);
+  if (mode != TCT_BP_ATOMIC && mode != TCT_BP_ATOMIC_DIRECT) {
+    set_error("tct_backproject_range: unknown mode");
+    return TCT_E_ARG;
+  }
+  if (!accumulate) {
+    st = launch_fill(xhat, m->nt, 0.f, (hipStream_t)s);
+    if (st != TCT_OK) return st;
+  }
+  return launch_pixel_walk(kModeBackAtomic, m, g, r->a0, r->na, entry, proj, xhat, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, r->tile_u, (hipStream_t)s, mode == TCT_BP_ATOMIC);
+}
+
 tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
                        tct_stream s) {
   tct_status st = check_pair(m, g);
@@ -248,7 +300,7 @@ tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* pr
   }
   DeviceGuard dg(m->device);
   if (mode == TCT_BP_GATHER)
-    return backproject_gather(m, g, proj, xhat, accumulate, entry, default_tile_u(), (hipStream_t)s);
+    return backproject_gather(m, g, proj, xhat, accumulate, entry, default_tile_u(), 0, g->na, (hipStream_t)s);
   if (mode != TCT_BP_ATOMIC && mode != TCT_BP_ATOMIC_DIRECT) {
     set_error("tct_backproject: unknown mode");
     return TCT_E_ARG;
@@ -380,6 +432,173 @@ tct_status tct_copy_f64(double* dst, const double* src, int32_t n, tct_stream s)
     return TCT_E_ARG;
   }
   return blas_copy_f64(dst, src, n, (hipStream_t)s);
+}
+
+tct_status tct_vecset_create(int32_t n, float* const* ptrs, const int64_t* lens, int device, tct_vecset** out) {
+  if (!out || n < 0 || (n > 0 && (!ptrs || !lens))) {
+    set_error("tct_vecset_create: bad arguments");
+    return TCT_E_ARG;
+  }
+  *out = nullptr;
+  for (int k = 0; k < n; ++k)
+    if (!ptrs[k] || lens[k] < 0) {
+      set_error("tct_vecset_create: null vector or negative length");
+      return TCT_E_ARG;
+    }
+  DeviceGuard dg(device);
+  tct_vecset* v = new tct_vecset();
+  v->device = device;
+  v->n = n;
+  v->ptrs.assign(ptrs, ptrs + n);
+  v->lens.assign(lens, lens + n);
+  size_t np = sizeof(float*) * (size_t)std::max(n, 1), nl = sizeof(int64_t) * (size_t)std::max(n, 1);
+  if (hipMalloc((void**)&v->d_ptrs, np) != hipSuccess || hipMalloc((void**)&v->d_lens, nl) != hipSuccess ||
+      (n > 0 && (hipMemcpy(v->d_ptrs, ptrs, sizeof(float*) * n, hipMemcpyHostToDevice) != hipSuccess ||
+                 hipMemcpy(v->d_lens, lens, sizeof(int64_t) * n, hipMemcpyHostToDevice) != hipSuccess))) {
+    if (v->d_ptrs) (void)hipFree(v->d_ptrs);
+    if (v->d_lens) (void)hipFree(v->d_lens);
+    delete v;
+    set_error("tct_vecset_create: device allocation failed");
+    return TCT_E_NOMEM;
+  }
+  *out = v;
+  return TCT_OK;
+}
+
+void tct_vecset_destroy(tct_vecset* v) {
+  if (!v) return;
+  DeviceGuard dg(v->device);
+  if (v->d_ptrs) (void)hipFree(v->d_ptrs);
+  if (v->d_lens) (void)hipFree(v->d_lens);
+  delete v;
+}
+
+namespace {
+tct_status check_sets(const tct_vecset* a, const tct_vecset* b, const char* what) {
+  if (!a || !b || a->n != b->n || a->device != b->device) {
+    set_error(std::string(what) + ": vector sets differ in count or device");
+    return TCT_E_ARG;
+  }
+  for (int k = 0; k < a->n; ++k)
+    if (a->lens[k] != b->lens[k]) {
+      set_error(std::string(what) + ": vector lengths differ at " + std::to_string(k));
+      return TCT_E_ARG;
+    }
+  return TCT_OK;
+}
+}  // namespace
+
+tct_status tct_vecset_dot(const tct_vecset* a, const tct_vecset* b, double* results, double* workspace,
+                          tct_stream s) {
+  tct_status st = check_sets(a, b, "tct_vecset_dot");
+  if (st != TCT_OK) return st;
+  if (!results || !workspace) {
+    set_error("tct_vecset_dot: null output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(a->device);
+  return vecset_dot(a, b, results, workspace, (hipStream_t)s);
+}
+
+tct_status tct_vecset_axpy_ratio(const tct_vecset* y, const tct_vecset* x, const double* num, const double* den,
+                                 double sign, tct_stream s) {
+  tct_status st = check_sets(y, x, "tct_vecset_axpy_ratio");
+  if (st != TCT_OK) return st;
+  if (!num || !den) {
+    set_error("tct_vecset_axpy_ratio: null scalars");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(y->device);
+  return vecset_axpy_ratio(y, x, num, den, sign, (hipStream_t)s);
+}
+
+tct_status tct_vecset_xpay_ratio(const tct_vecset* p, const tct_vecset* x, const double* num, const double* den,
+                                 tct_stream s) {
+  tct_status st = check_sets(p, x, "tct_vecset_xpay_ratio");
+  if (st != TCT_OK) return st;
+  if (!num || !den) {
+    set_error("tct_vecset_xpay_ratio: null scalars");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(p->device);
+  return vecset_xpay_ratio(p, x, num, den, (hipStream_t)s);
+}
+
+tct_status tct_vecset_fill(const tct_vecset* y, float value, tct_stream s) {
+  if (!y) {
+    set_error("tct_vecset_fill: null set");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(y->device);
+  return vecset_fill(y, value, (hipStream_t)s);
+}
+
+tct_status tct_batch_create(const tct_mesh* const* meshes, const tct_geom* const* geoms, int32_t n,
+                            const int32_t* tile_u, int32_t* const* entries, tct_batch** out) {
+  if (!out || !meshes || !geoms || n <= 0) {
+    set_error("tct_batch_create: bad arguments");
+    return TCT_E_ARG;
+  }
+  *out = nullptr;
+  for (int k = 0; k < n; ++k) {
+    tct_status st = check_pair(meshes[k], geoms[k]);
+    if (st != TCT_OK) return st;
+    if (meshes[k]->device != meshes[0]->device) {
+      set_error("tct_batch_create: problems on different devices");
+      return TCT_E_ARG;
+    }
+    if (tile_u) {
+      int t = tile_u[k];
+      if (t != 4 && t != 8 && t != 16 && t != 32 && t != 64) {
+        set_error("tct_batch_create: tile_u must be 4, 8, 16, 32 or 64");
+        return TCT_E_ARG;
+      }
+    }
+  }
+  DeviceGuard dg(meshes[0]->device);
+  return batch_build(meshes, geoms, n, tile_u, entries, out);
+}
+
+namespace {
+tct_status check_batch_sets(const tct_batch* b, const tct_vecset* xs, const tct_vecset* ps) {
+  if (!b || !xs || !ps || xs->n != b->n || ps->n != b->n || xs->device != b->device || ps->device != b->device) {
+    set_error("batch: vector sets do not match the batch");
+    return TCT_E_ARG;
+  }
+  for (int k = 0; k < b->n; ++k)
+    if (xs->lens[k] != b->meshes[k]->nt || ps->lens[k] != b->geoms[k]->nrays()) {
+      set_error("batch: vector " + std::to_string(k) + " has the wrong length");
+      return TCT_E_ARG;
+    }
+  return TCT_OK;
+}
+}  // namespace
+
+tct_status tct_batch_forward(tct_batch* b, const tct_vecset* x, const tct_vecset* proj, tct_stream s) {
+  tct_status st = check_batch_sets(b, x, proj);
+  if (st != TCT_OK) return st;
+  DeviceGuard dg(b->device);
+  return batch_walk(b, kModeForward, x, proj, (hipStream_t)s);
+}
+
+tct_status tct_batch_backproject(tct_batch* b, const tct_vecset* proj, const tct_vecset* xhat, int accumulate,
+                                 tct_stream s) {
+  tct_status st = check_batch_sets(b, xhat, proj);
+  if (st != TCT_OK) return st;
+  DeviceGuard dg(b->device);
+  if (!accumulate) {
+    st = vecset_fill(xhat, 0.f, (hipStream_t)s);
+    if (st != TCT_OK) return st;
+  }
+  return batch_walk(b, kModeBackAtomic, proj, xhat, (hipStream_t)s);
+}
+
+int64_t tct_batch_items(const tct_batch* b) { return b ? b->total_items : 0; }
+
+void tct_batch_destroy(tct_batch* b) {
+  if (!b) return;
+  DeviceGuard dg(b->device);
+  batch_free(b);
 }
 
 }  // extern "C"

@@ -108,6 +108,27 @@ struct tct_mesh {
   }
 };
 
+struct tct_vecset {
+  int device = 0;
+  int n = 0;
+  std::vector<float*> ptrs;
+  std::vector<int64_t> lens;
+  float** d_ptrs = nullptr;
+  int64_t* d_lens = nullptr;
+};
+
+struct tct_batch {
+  int device = 0;
+  int n = 0;
+  std::vector<const tct_mesh*> meshes;
+  std::vector<const tct_geom*> geoms;
+  std::vector<int> tile_u;
+  void* d_desc = nullptr;  // device BatchDesc[n], most expensive blocks first
+  int64_t total_items = 0;
+  unsigned long long* d_counter = nullptr;
+  int grid_fwd = 0, grid_bwd = 0;  // persistent grid sizes
+};
+
 struct tct_geom {
   int device = 0;
   tct_cone cone;

@@ -109,10 +109,10 @@ tct_status exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_
 }
 
 tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
-                              const int32_t* entry, int tile_u, hipStream_t s) {
+                              const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s) {
   const int64_t rays_per_angle = (int64_t)g->cone.nu * g->cone.nv;
   // Chunk of angles: about 4M rays, at least one angle.
-  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(g->na, ((int64_t)1 << 22) / rays_per_angle));
+  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(a_count, ((int64_t)1 << 22) / rays_per_angle));
   AsyncBuf<double> acc(s);
   AsyncBuf<int64_t> counts(s), offsets(s);
   AsyncBuf<int32_t> keys(s), keys_sorted(s);
@@ -122,8 +122,9 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
   hipLaunchKernelGGL(zero_f64_kernel, dim3((m->nt + 255) / 256), dim3(256), 0, s, acc.p, (int64_t)m->nt);
   TCT_HIP(hipGetLastError());
   const int bits = key_bits(m->nt);
-  for (int a0 = 0; a0 < g->na; a0 += chunk) {
-    int na_c = std::min(chunk, g->na - a0);
+  const int a_end = a_begin + a_count;
+  for (int a0 = a_begin; a0 < a_end; a0 += chunk) {
+    int na_c = std::min(chunk, a_end - a0);
     int64_t nr = (int64_t)na_c * rays_per_angle;
     TCT_HIP(counts.ensure(nr));
     TCT_HIP(offsets.ensure(nr + 1));

@@ -31,7 +31,19 @@ tct_status launch_fill(float* p, int64_t n, float v, hipStream_t s);
 tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s);
 
 tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
-                              const int32_t* entry, int tile_u, hipStream_t s);
+                              const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s);
+
+tct_status batch_build(const tct_mesh* const* meshes, const tct_geom* const* geoms, int32_t n, const int32_t* tile_u,
+                       int32_t* const* entries, tct_batch** out);
+void batch_free(tct_batch* b);
+tct_status batch_walk(tct_batch* b, int mode, const tct_vecset* in, const tct_vecset* out, hipStream_t s);
+
+tct_status vecset_dot(const tct_vecset* a, const tct_vecset* b, double* results, double* workspace, hipStream_t s);
+tct_status vecset_axpy_ratio(const tct_vecset* y, const tct_vecset* x, const double* num, const double* den,
+                             double sign, hipStream_t s);
+tct_status vecset_xpay_ratio(const tct_vecset* p, const tct_vecset* x, const double* num, const double* den,
+                             hipStream_t s);
+tct_status vecset_fill(const tct_vecset* y, float v, hipStream_t s);
 
 tct_status exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_host, hipStream_t s);
 

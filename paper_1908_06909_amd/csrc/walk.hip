@@ -406,10 +406,12 @@ __device__ __forceinline__ void flush_stats(const MeshView& M, LaneStats& st, in
   }
 }
 
-// Pixel blocks: a 256-thread block covers 16 x 16 pixels of one angle, as
-// four 8 x 8 wavefronts arranged 2 x 2.
+// Pixel blocks: a 256-thread block is four wavefronts arranged 2 x 2, each
+// covering a tile of tu x tv = 64 pixels of one angle (8 x 8 by default), so a
+// block covers (2 tu) x (2 tv) pixels.
 struct TileMap {
   int nbu, nbv;  // blocks along u and v
+  int tu, tv;    // wave tile
 };
 
 __device__ __forceinline__ bool tile_ray(const GeomView& g, const TileMap& tm, int64_t block, int tid, int a0,
@@ -420,33 +422,39 @@ __device__ __forceinline__ bool tile_ray(const GeomView& g, const TileMap& tm, i
   int bv = (int)(rem / tm.nbu), bu = (int)(rem - (int64_t)bv * tm.nbu);
   int wave = tid >> 6, lane = tid & 63;
   *a = a0 + (int)aa;
-  *i = bu * 16 + (wave & 1) * 8 + (lane & 7);
-  *j = bv * 16 + (wave >> 1) * 8 + (lane >> 3);
+  *i = bu * 2 * tm.tu + (wave & 1) * tm.tu + lane % tm.tu;
+  *j = bv * 2 * tm.tv + (wave >> 1) * tm.tv + lane / tm.tu;
   return aa < na_chunk && *i < g.nu && *j < g.nv;
 }
 
-}  // namespace
+// Inputs and outputs of one pixel-block walk (which fields are used depends on the mode).
+struct BlockIO {
+  const int32_t* entry;
+  const float* in;
+  float* out_f32;
+  int32_t* out_i32;
+  int64_t* counts;
+  const int64_t* offsets;
+  int32_t* keys;
+  float* vals;
+  int lds_table;
+};
 
-// ---------------------------------------------------------------- kernels
-
-// One launch per mode over the pixel rays of angles [a0, a0 + na_chunk).
+// Walk the rays of pixel block `block` (of angles [a0, a0 + na_chunk)).
 //   kModeEntry:      out_i32[rid] = entry face (or -1)
 //   kModeForward:    out_f32[rid] = sum_i a_ij x_i
-//   kModeBackAtomic: xhat[i] += a_ij y_j
+//   kModeBackAtomic: xhat[i] += a_ij y_j (through the LDS table when enabled)
 //   kModeCountPos:   counts[rid - rid0] = positive-length visits
 //   kModeGatherFill: keys/vals at offsets[rid - rid0]
+// Every thread of the block must call it (the backprojection synchronises).
 template <int MODE>
-__global__ __launch_bounds__(256) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
-                                                         const int32_t* entry, const float* in, float* out_f32,
-                                                         int32_t* out_i32, int64_t* counts, const int64_t* offsets,
-                                                         int32_t* keys, float* vals, int lds_table) {
+__device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G, const TileMap& tm, int64_t block,
+                                           int a0, int na_chunk, const BlockIO& io, int* tkeys, float* tvals) {
   int a, i, j;
-  bool active = tile_ray(G, tm, blockIdx.x, threadIdx.x, a0, na_chunk, &a, &i, &j);
+  bool active = tile_ray(G, tm, block, threadIdx.x, a0, na_chunk, &a, &i, &j);
   LaneStats st;
   if constexpr (MODE == kModeBackAtomic) {
-    __shared__ int tkeys[kLdsSlots];
-    __shared__ float tvals[kLdsSlots];
-    if (lds_table) {
+    if (io.lds_table) {
       for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
         tkeys[k] = -1;
         tvals[k] = 0.f;
@@ -456,48 +464,115 @@ __global__ __launch_bounds__(256) void pixel_walk_kernel(MeshView M, GeomView G,
     if (active) {
       int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
       Ray r = cone_ray(G, a, i, j);
-      int e = entry ? entry[rid] : find_entry(M, r, st);
+      int e = io.entry ? io.entry[rid] : find_entry(M, r, st);
       WalkOut<MODE> o;
-      o.xhat = out_f32;
-      if (lds_table) {
+      o.xhat = io.out_f32;
+      if (io.lds_table) {
         o.lds_keys = tkeys;
         o.lds_vals = tvals;
       }
-      o.weight = in[rid] * r.dn;
+      o.weight = io.in[rid] * r.dn;
       if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, e, o, st);
     }
-    if (lds_table) {
+    if (io.lds_table) {
       __syncthreads();
       for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x)
-        if (tkeys[k] >= 0) unsafeAtomicAdd(out_f32 + tkeys[k], tvals[k]);
+        if (tkeys[k] >= 0) unsafeAtomicAdd(io.out_f32 + tkeys[k], tvals[k]);
+      __syncthreads();
     }
   } else if (active) {
     int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
     int64_t rid0 = (int64_t)a0 * G.nv * G.nu;
     Ray r = cone_ray(G, a, i, j);
-    int e = (entry && MODE != kModeEntry) ? entry[rid] : find_entry(M, r, st);
+    int e = (io.entry && MODE != kModeEntry) ? io.entry[rid] : find_entry(M, r, st);
     if constexpr (MODE == kModeEntry) {
-      out_i32[rid] = e;
+      io.out_i32[rid] = e;
     } else if constexpr (MODE == kModeForward) {
       WalkOut<MODE> o;
-      o.x = in;
+      o.x = io.in;
       if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
-      out_f32[rid] = (float)(o.acc * (double)r.dn);
+      io.out_f32[rid] = (float)(o.acc * (double)r.dn);
     } else if constexpr (MODE == kModeCountPos) {
       WalkOut<MODE> o;
       if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
-      counts[rid - rid0] = o.count;
+      io.counts[rid - rid0] = o.count;
     } else if constexpr (MODE == kModeGatherFill) {
       WalkOut<MODE> o;
-      o.weight = in[rid] * r.dn;
-      o.out_tet = keys;
-      o.out_len = vals;
-      o.cursor = offsets[rid - rid0];
+      o.weight = io.in[rid] * r.dn;
+      o.out_tet = io.keys;
+      o.out_len = io.vals;
+      o.cursor = io.offsets[rid - rid0];
       if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
     }
   }
   flush_stats(M, st, active ? 1 : 0);
 }
+
+}  // namespace
+
+// ---------------------------------------------------------------- kernels
+
+template <int MODE>
+__global__ __launch_bounds__(256) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
+                                                         BlockIO io) {
+  if constexpr (MODE == kModeBackAtomic) {
+    __shared__ int tkeys[kLdsSlots];
+    __shared__ float tvals[kLdsSlots];
+    walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, tkeys, tvals);
+  } else {
+    walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, nullptr, nullptr);
+  }
+}
+
+// Batched problems: one persistent launch pulls pixel blocks of every
+// problem from a device work counter.  Problems are listed most expensive
+// block first, so long walks start early and short ones fill the tail.
+struct BatchDesc {
+  MeshView M;
+  GeomView G;
+  TileMap tm;
+  int64_t item_begin;  // first queue item of this problem
+  const int32_t* entry;
+  int user;  // index of the problem in the caller's lists
+  int lds_table;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void batch_walk_kernel(const BatchDesc* D, int nprob, int64_t total,
+                                                         unsigned long long* counter, const float* const* ins,
+                                                         float* const* outs) {
+  __shared__ long long s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+    __syncthreads();
+    long long item = s_item;
+    if (item >= total) break;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (D[mid].item_begin <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const BatchDesc& d = D[lo];
+    BlockIO io{};
+    io.entry = d.entry;
+    io.in = ins[d.user];
+    io.out_f32 = outs[d.user];
+    io.lds_table = d.lds_table;
+    if constexpr (MODE == kModeBackAtomic) {
+      __shared__ int tkeys[kLdsSlots];
+      __shared__ float tvals[kLdsSlots];
+      walk_block<MODE>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
+    } else {
+      walk_block<MODE>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
 // Listed rays (trace): either pixel ray ids, or explicit S/P/U/V arrays.
 template <int MODE>
@@ -558,10 +633,13 @@ __global__ void permute_kernel(const float* in, float* out, const int32_t* perm,
 
 // ---------------------------------------------------------------- launchers
 
-static TileMap make_tiles(const GeomView& g) {
+static TileMap make_tiles(const GeomView& g, int tile_u) {
   TileMap t;
-  t.nbu = (g.nu + 15) / 16;
-  t.nbv = (g.nv + 15) / 16;
+  if (tile_u != 4 && tile_u != 8 && tile_u != 16 && tile_u != 32 && tile_u != 64) tile_u = 8;
+  t.tu = tile_u;
+  t.tv = 64 / tile_u;
+  t.nbu = (g.nu + 2 * t.tu - 1) / (2 * t.tu);
+  t.nbv = (g.nv + 2 * t.tv - 1) / (2 * t.tv);
   return t;
 }
 
@@ -569,20 +647,19 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
                              const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
                              int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
                              hipStream_t s, int lds_table) {
-  (void)tile_u;
   MeshView M = m->view();
   GeomView G = g->view();
-  TileMap tm = make_tiles(G);
+  TileMap tm = make_tiles(G, tile_u);
   int64_t blocks = (int64_t)tm.nbu * tm.nbv * na_chunk;
   if (blocks <= 0) return TCT_OK;
   if (blocks > 0x7fffffff) {
     set_error("too many rays in one launch");
     return TCT_E_ARG;
   }
+  BlockIO io{entry, in, out_f32, out_i32, counts, offsets, keys, vals, lds_table};
   dim3 grid((unsigned)blocks), block(256);
-#define TCT_LAUNCH(MODE_)                                                                                        \
-  hipLaunchKernelGGL(pixel_walk_kernel<MODE_>, grid, block, 0, s, M, G, tm, a0, na_chunk, entry, in, out_f32, \
-                     out_i32, counts, offsets, keys, vals, lds_table)
+#define TCT_LAUNCH(MODE_) \
+  hipLaunchKernelGGL(pixel_walk_kernel<MODE_>, grid, block, 0, s, M, G, tm, a0, na_chunk, io)
   switch (mode) {
     case kModeEntry:
       TCT_LAUNCH(kModeEntry);
@@ -641,6 +718,90 @@ tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float*
   }
   return launch_pixel_walk(kModeBackAtomic, m, g, 0, g->na, entry, proj, xhat, nullptr, nullptr, nullptr, nullptr,
                            nullptr, tile_u, s, lds_table);
+}
+
+// ---------------------------------------------------------------- batches
+
+tct_status batch_build(const tct_mesh* const* meshes, const tct_geom* const* geoms, int32_t n, const int32_t* tile_u,
+                       int32_t* const* entries, tct_batch** out) {
+  *out = nullptr;
+  tct_batch* b = new tct_batch();
+  b->n = n;
+  b->device = meshes[0]->device;
+  std::vector<BatchDesc> desc(n);
+  std::vector<double> cost(n);
+  for (int p = 0; p < n; ++p) {
+    b->meshes.push_back(meshes[p]);
+    b->geoms.push_back(geoms[p]);
+    b->tile_u.push_back(tile_u ? tile_u[p] : default_tile_u());
+    BatchDesc& d = desc[p];
+    d.M = meshes[p]->view();
+    d.G = geoms[p]->view();
+    d.tm = make_tiles(d.G, b->tile_u[p]);
+    d.entry = entries ? entries[p] : nullptr;
+    d.user = p;
+    d.lds_table = 1;
+    // Walk length per ray grows like the mesh's linear resolution.
+    cost[p] = std::cbrt((double)meshes[p]->nt);
+  }
+  std::vector<int> order(n);
+  for (int p = 0; p < n; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+  std::vector<BatchDesc> sorted(n);
+  int64_t item = 0;
+  for (int k = 0; k < n; ++k) {
+    sorted[k] = desc[order[k]];
+    sorted[k].item_begin = item;
+    item += (int64_t)sorted[k].tm.nbu * sorted[k].tm.nbv * sorted[k].G.na;
+  }
+  b->total_items = item;
+  auto fail = [&](hipError_t e, const char* what) {
+    batch_free(b);
+    return hip_fail(e, what);
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * (size_t)n)) != hipSuccess) return fail(e, "hipMalloc(batch)");
+  if ((e = hipMemcpy(b->d_desc, sorted.data(), sizeof(BatchDesc) * (size_t)n, hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e, "hipMemcpy(batch)");
+  if ((e = hipMalloc((void**)&b->d_counter, sizeof(unsigned long long))) != hipSuccess)
+    return fail(e, "hipMalloc(batch counter)");
+  int cus = 0, occ_f = 0, occ_b = 0;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device)) != hipSuccess)
+    return fail(e, "hipDeviceGetAttribute");
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, batch_walk_kernel<kModeForward>, 256, 0)) !=
+      hipSuccess)
+    return fail(e, "occupancy");
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_b, batch_walk_kernel<kModeBackAtomic>, 256, 0)) !=
+      hipSuccess)
+    return fail(e, "occupancy");
+  b->grid_fwd = std::max(1, cus * std::max(1, occ_f));
+  b->grid_bwd = std::max(1, cus * std::max(1, occ_b));
+  *out = b;
+  return TCT_OK;
+}
+
+void batch_free(tct_batch* b) {
+  if (!b) return;
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_counter) (void)hipFree(b->d_counter);
+  delete b;
+}
+
+tct_status batch_walk(tct_batch* b, int mode, const tct_vecset* in, const tct_vecset* out, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, b->d_counter);
+  const BatchDesc* D = (const BatchDesc*)b->d_desc;
+  if (mode == kModeForward) {
+    hipLaunchKernelGGL(batch_walk_kernel<kModeForward>, dim3(b->grid_fwd), dim3(256), 0, s, D, b->n, b->total_items,
+                       b->d_counter, (const float* const*)in->d_ptrs, out->d_ptrs);
+  } else if (mode == kModeBackAtomic) {
+    hipLaunchKernelGGL(batch_walk_kernel<kModeBackAtomic>, dim3(b->grid_bwd), dim3(256), 0, s, D, b->n,
+                       b->total_items, b->d_counter, (const float* const*)in->d_ptrs, out->d_ptrs);
+  } else {
+    set_error("batch_walk: unsupported mode");
+    return TCT_E_ARG;
+  }
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
 }
 
 tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s) {
