@@ -34,10 +34,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", type=int, default=1, help="workload index (1 = the benchmark configuration)")
+    ap.add_argument("--angles", type=int, default=0,
+                    help="use only the first N angles of the workload (profiling passes); 0 = all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--gather", action="store_true")
     ap.add_argument("--json-extra", default=None)
+    ap.add_argument("--batch-cgls", type=int, default=0, metavar="NPROB",
+                    help="instead of the default line: batched (one persistent launch per direction, graph-replayed) "
+                         "vs plain per-problem CGLS iterations/s on the first NPROB problems of the 32-problem ladder")
+    ap.add_argument("--tune", action="store_true", help="with --batch-cgls: autotune the tile width per problem")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes (3 times) to calibrate HBM counters")
     return ap.parse_args()
@@ -79,6 +85,86 @@ def cpu_baseline(w, budget_s):
     }
 
 
+def batch_cgls_bench(args):
+    """Batched vs plain CGLS on the problem ladder (independent meshes and geometries)."""
+    import torch
+
+    import paper_1908_06909_amd as tct
+    import synth
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    probs = []
+    for b in range(args.batch_cgls):
+        w = synth.batch_problem(b)
+        mesh = tct.TetMesh(w.verts, w.tets, device=dev)
+        geom = tct.ConeGeometry(w.cone, w.angles, device=dev)
+        P = tct.Projector(mesh, geom)
+        x = mesh.to_internal(torch.as_tensor(w.x, device=dev))
+        bvec = P.forward(x).reshape(-1).clone()
+        probs.append((w, P, bvec))
+        del w
+    setup_s = time.time() - t0
+    Ps = [p[1] for p in probs]
+    bs = [p[2] for p in probs]
+    tiles = None
+    tune_s = 0.0
+    if args.tune:
+        t0 = time.time()
+        tiles = tct.autotune.tune_all(Ps, n_angles=2, reps=1)
+        tune_s = time.time() - t0
+    B = tct.BatchProjector(Ps, tiles)
+
+    def timed(fn, iters):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn(iters)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    K, W = max(1, args.steps), args.warmup
+    bat = tct.BatchCGLS(B, bs)
+    bat.capture()
+    bat.run(W, graph=True)
+    t_bat = timed(lambda k: bat.run(k, graph=True), K)
+    rr_bat = (bat.rr / bat.rr0).cpu().numpy()
+    del bat
+    pl = tct.PlainCGLS(Ps, bs)
+    pl.run(W)
+    t_pl = timed(pl.run, K)
+    rr_pl = np.array([float(s.hist[-1].item() / s.hist[0].item()) for s in pl.solvers])
+    segs = 0
+    for P in Ps:
+        segs += P.mesh.stats(reset=True)["segments"]
+    out = {
+        "metric": "batched vs plain CGLS iterations/s",
+        "value": K / t_bat,
+        "unit": "CGLS iterations/s (all problems)",
+        "plain_value": K / t_pl,
+        "speedup": t_pl / t_bat,
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_iteration_batched": t_bat * 1e3 / K,
+        "ms_per_iteration_plain": t_pl * 1e3 / K,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batch ladder, first {len(Ps)} problems",
+            "tets": int(sum(P.nt for P in Ps)),
+            "rays": int(sum(P.geom.nrays for P in Ps)),
+            "tile_u": tiles,
+            "queue_items": B.items,
+        },
+        "residual_ratio_batched_last": float(np.max(rr_bat)),
+        "residual_ratio_plain_last": float(np.max(rr_pl)),
+        "setup_s": setup_s,
+        "tune_s": tune_s,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -100,9 +186,16 @@ def main():
     import synth
     from paper_1908_06909_amd import ConeGeometry, Projector, TetMesh
 
+    if args.batch_cgls:
+        batch_cgls_bench(args)
+        return
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     w = synth.config(args.workload)
+    if args.angles:
+        w.angles = w.angles[: args.angles]
+        w.name += f"_first{args.angles}angles"
     t0 = time.time()
     mesh = TetMesh(w.verts, w.tets, device=dev)
     geom = ConeGeometry(w.cone, w.angles, device=dev)

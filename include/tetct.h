@@ -90,9 +90,11 @@ typedef struct {
  * included); fp64_stage counts sign tests the float32 filter could not
  * certify; exact_stage those the float64 filter could not certify either;
  * perturbed_ties those decided by the eps*U / eps^2*V terms; failed counts
- * rays that stopped without leaving the mesh (should stay 0). */
+ * rays that stopped without leaving the mesh (should stay 0); grazing_fp64
+ * counts exit crossings recomputed in float64 because the face was nearly
+ * parallel to the ray. */
 typedef struct {
-  int64_t rays, segments, zero_len, fp64_stage, exact_stage, perturbed_ties, failed, reserved;
+  int64_t rays, segments, zero_len, fp64_stage, exact_stage, perturbed_ties, failed, grazing_fp64;
 } tct_stats;
 
 /* ---------------------------------------------------------------- mesh */

@@ -52,10 +52,10 @@ class tct_range(C.Structure):
 
 class tct_stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in
-                ("rays", "segments", "zero_len", "fp64_stage", "exact_stage", "perturbed_ties", "failed", "reserved")]
+                ("rays", "segments", "zero_len", "fp64_stage", "exact_stage", "perturbed_ties", "failed", "grazing_fp64")]
 
     def as_dict(self):
-        return {n: int(getattr(self, n)) for n, _ in self._fields_ if n != "reserved"}
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 # name -> (restype, argtypes); pointers are passed as integers (c_void_p).

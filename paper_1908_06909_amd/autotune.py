@@ -11,6 +11,7 @@ file keyed by device, mesh size and detector/angle shape.
 
 from __future__ import annotations
 
+import ctypes as C
 import json
 import os
 from typing import Dict, Optional, Sequence
@@ -38,7 +39,7 @@ def _time_tile(P: Projector, tile_u: int, angles: Sequence[int], x, y, xhat, pro
 
     def once():
         for a in angles:
-            r = tct_range(a, 1, tile_u)
+            r = C.byref(tct_range(a, 1, tile_u))
             call("tct_forward_range", P.mesh.handle, P.geom.handle, x.data_ptr(), proj.data_ptr(), entry, r,
                  _stream(P.device))
             call("tct_backproject_range", P.mesh.handle, P.geom.handle, y.data_ptr(), xhat.data_ptr(), TCT_BP_ATOMIC,

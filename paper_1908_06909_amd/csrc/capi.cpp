@@ -150,7 +150,7 @@ tct_status tct_stats_read(const tct_mesh* m, tct_stats* out, int reset) {
   out->exact_stage = (int64_t)h[kExactStage];
   out->perturbed_ties = (int64_t)h[kPerturbed];
   out->failed = (int64_t)h[kFailed];
-  out->reserved = 0;
+  out->grazing_fp64 = (int64_t)h[kGrazing];
   if (reset) {
     unsigned long long z[kNumCounters] = {0};
     TCT_HIP(hipMemcpy(m->d_counters, z, sizeof(z), hipMemcpyHostToDevice));

@@ -64,6 +64,7 @@ enum Counter {
   kExactStage,
   kPerturbed,
   kFailed,
+  kGrazing,
   kNumCounters = 8
 };
 

@@ -54,7 +54,7 @@ struct Ray {
 };
 
 struct LaneStats {
-  int steps = 0, zero = 0, fp64 = 0, exact = 0, pert = 0, failed = 0;
+  int steps = 0, zero = 0, fp64 = 0, exact = 0, pert = 0, failed = 0, grazing = 0;
 };
 
 __device__ __forceinline__ float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
@@ -239,7 +239,11 @@ __device__ __forceinline__ void lds_accumulate(int* keys, float* vals, int tet, 
     int k = keys[slot];
     if (k == -1) k = atomicCAS(keys + slot, -1, tet);
     if (k == -1 || k == tet) {
-      atomicAdd(vals + slot, v);
+      // The table pointer arrives as a generic pointer; cast it back to the
+      // LDS address space so the add is a native ds_add_f32 (through a
+      // generic pointer it becomes a flat atomic or a compare-and-swap loop).
+      __hip_atomic_fetch_add((__attribute__((address_space(3))) float*)(vals + slot), v, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
       return;
     }
   }
@@ -327,8 +331,9 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
     float dt;
     if (den * den >= kGrazingCos2 * r.dd * f3dot(n, n)) {
       float3 Q = make_float3(r.M.x + s_in * r.d.x, r.M.y + s_in * r.d.y, r.M.z + s_in * r.d.z);
-      dt = f3dot(f3sub(v, Q), n) / den;
+      dt = f3dot(f3sub(v, Q), n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
     } else {
+      st.grazing++;
       float3 ai = k == 2 ? a0 : (k == 0 ? a1 : a2);
       float3 aj = k == 2 ? a1 : (k == 0 ? a2 : a0);
       dt = (float)(crossing_s_fp64(r.S, r.P, v, ai, aj) - (double)s_in);
@@ -391,9 +396,9 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
 
 __device__ __forceinline__ void flush_stats(const MeshView& M, LaneStats& st, int active) {
   // Wave-level reduction, one atomic per counter per wave.
-  int v[7] = {active, st.steps, st.zero, st.fp64, st.exact, st.pert, st.failed};
+  int v[8] = {active, st.steps, st.zero, st.fp64, st.exact, st.pert, st.failed, st.grazing};
 #pragma unroll
-  for (int c = 0; c < 7; ++c) {
+  for (int c = 0; c < 8; ++c) {
     int x = v[c];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -401,7 +406,7 @@ __device__ __forceinline__ void flush_stats(const MeshView& M, LaneStats& st, in
   }
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int c = 0; c < 7; ++c)
+    for (int c = 0; c < 8; ++c)
       if (v[c]) atomicAdd(M.counters + c, (unsigned long long)v[c]);
   }
 }

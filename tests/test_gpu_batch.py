@@ -1,5 +1,6 @@
 """Batched persistent launches, vector sets, angle ranges, graph replay and the tile autotuner."""
 
+import ctypes
 import json
 import os
 
@@ -86,13 +87,13 @@ def test_range_launches_assemble_the_full_projection():
     na = P.geom.na
     for a0, cnt, tile in ((0, 5, 16), (5, 4, 4), (9, na - 9, 64)):
         call("tct_forward_range", P.mesh.handle, P.geom.handle, x.data_ptr(), part.data_ptr(), P.entry.data_ptr(),
-             tct_range(a0, cnt, tile), s)
+             ctypes.byref(tct_range(a0, cnt, tile)), s)
     assert torch.equal(part, full)
     y = torch.rand(P.geom.nrays, device=DEV)
     acc = torch.zeros(P.nt, device=DEV)
     for a0, cnt in ((0, 7), (7, na - 7)):
         call("tct_backproject_range", P.mesh.handle, P.geom.handle, y.data_ptr(), acc.data_ptr(), 1, 1,
-             P.entry.data_ptr(), tct_range(a0, cnt, 8), s)
+             P.entry.data_ptr(), ctypes.byref(tct_range(a0, cnt, 8)), s)
     whole = P.backproject(y, mode="gather")
     assert torch.allclose(acc, whole, rtol=1e-6, atol=1e-6)
 
