@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -45,6 +47,7 @@ struct MeshView {
   int nt;
   int nb;
   unsigned long long* counters;  // tct_stats fields, int64 each
+  float extent;                  // largest |coordinate| of any node
 };
 
 // Cone-beam frames: frame[12 a + 0..11] = S, D, U, V of angle a.
@@ -105,6 +108,8 @@ struct tct_mesh {
     v.nt = nt;
     v.nb = nb;
     v.counters = d_counters;
+    v.extent = 0.f;
+    for (int k = 0; k < 3; ++k) v.extent = std::max(v.extent, std::max(std::fabs(lo[k]), std::fabs(hi[k])));
     return v;
   }
 };

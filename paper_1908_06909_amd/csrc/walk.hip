@@ -46,11 +46,15 @@ constexpr float kFilterAbs = 7.888609052210118e-31f;  // 2^-100
 
 struct Ray {
   float3 S, P, U, V;
-  float3 d;   // fl(P - S)
-  float3 ad;  // |d|
-  float3 M;   // fl(S + d / 2): reference point near the mesh for ray parameters
-  float dn;   // |d| (Euclidean)
-  float dd;   // |d|^2
+  float3 d;    // d_hi = fl(P - S)
+  float3 dlo;  // P - S - d_hi (exact)
+  float3 ad;   // |d_hi|
+  float3 M;    // M_hi, M_lo: the ray point at t = 1/2 as an unevaluated sum
+  float3 Mlo;
+  float dn;    // |d| (Euclidean)
+  float dd;    // |d|^2
+  float dinf;  // max |d_i|
+  float kR;    // 64 u^2 R, R bounding every coordinate met on this ray (walk filter)
 };
 
 struct LaneStats {
@@ -65,16 +69,41 @@ __device__ __forceinline__ float3 f3cross(float3 a, float3 b) {
 __device__ __forceinline__ float3 f3abs(float3 a) { return make_float3(fabsf(a.x), fabsf(a.y), fabsf(a.z)); }
 __device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.y, a.z, a.w); }
 
-__device__ __forceinline__ void finish_ray(Ray& r) {
-  r.d = f3sub(r.P, r.S);
+// Knuth's two-sum: a + b = s + e exactly (round to nearest, no overflow).
+__device__ __forceinline__ void two_sum_f(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bv = s - a;
+  float av = s - bv;
+  e = (a - av) + (b - bv);
+}
+
+// The ray is carried with an exact direction d = d_hi + d_lo and an almost
+// exact point M = M_hi + M_lo at t = 1/2 (error O(u^2 |M|)), so positions on
+// it near the mesh can be formed to a relative accuracy set by their distance
+// to the mesh features rather than by the distance to the source.
+__device__ __forceinline__ void finish_ray(Ray& r, float mesh_extent) {
+  float e;
+  two_sum_f(r.P.x, -r.S.x, r.d.x, r.dlo.x);
+  two_sum_f(r.P.y, -r.S.y, r.d.y, r.dlo.y);
+  two_sum_f(r.P.z, -r.S.z, r.d.z, r.dlo.z);
+  two_sum_f(r.S.x, 0.5f * r.d.x, r.M.x, e);
+  r.Mlo.x = e + 0.5f * r.dlo.x;
+  two_sum_f(r.S.y, 0.5f * r.d.y, r.M.y, e);
+  r.Mlo.y = e + 0.5f * r.dlo.y;
+  two_sum_f(r.S.z, 0.5f * r.d.z, r.M.z, e);
+  r.Mlo.z = e + 0.5f * r.dlo.z;
   r.ad = f3abs(r.d);
-  r.M = make_float3(r.S.x + 0.5f * r.d.x, r.S.y + 0.5f * r.d.y, r.S.z + 0.5f * r.d.z);
   r.dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
   r.dn = sqrtf(r.dd);
+  r.dinf = fmaxf(r.ad.x, fmaxf(r.ad.y, r.ad.z));
+  float sp = fmaxf(fmaxf(fmaxf(fabsf(r.S.x), fabsf(r.S.y)), fmaxf(fabsf(r.S.z), fabsf(r.P.x))),
+                   fmaxf(fabsf(r.P.y), fabsf(r.P.z)));
+  float R = (fmaxf(sp, mesh_extent) + r.dinf) * 1.0001f;
+  r.kR = 64.0f * 3.552713678800501e-15f * R;  // 64 u^2 R with u = 2^-24
 }
 
 // Pixel ray: P = fl(fl(D + fl(u U)) + fl(v V)) per component, no contraction.
-__device__ __forceinline__ Ray cone_ray(const GeomView& g, int a, int i, int j) {
+__device__ __forceinline__ Ray cone_ray(const GeomView& g, float mesh_extent, int a, int i, int j) {
   const float* f = g.frame + 12 * a;
   float u = g.ut[i], v = g.vt[j];
   Ray r;
@@ -84,7 +113,7 @@ __device__ __forceinline__ Ray cone_ray(const GeomView& g, int a, int i, int j) 
   r.P.x = __fadd_rn(__fadd_rn(f[3], __fmul_rn(u, f[6])), __fmul_rn(v, f[9]));
   r.P.y = __fadd_rn(__fadd_rn(f[4], __fmul_rn(u, f[7])), __fmul_rn(v, f[10]));
   r.P.z = __fadd_rn(__fadd_rn(f[5], __fmul_rn(u, f[8])), __fmul_rn(v, f[11]));
-  finish_ray(r);
+  finish_ray(r, mesh_extent);
   return r;
 }
 
@@ -113,9 +142,37 @@ __device__ __noinline__ double crossing_s_fp64(float3 S, float3 P, float3 on, fl
 }
 
 // cos^2 of the angle between the ray and a face normal below which the
-// crossing is recomputed in float64: the float32 error of a crossing is about
-// 2^-23 |Q| / cos, so 1/8 keeps it near 1e-6 of the chord.
-constexpr float kGrazingCos2 = 1.0f / 64.0f;
+// crossing is recomputed in float64.  With the vertex offset D accurate to a
+// few ulps of |D| (walk_ray), the float32 crossing moves by about c u h / cos
+// (h the face diameter, c ~ 5 from the rounded normal), i.e. 2e-5 h at
+// cos = 1/64, the same absolute size as the rounding of the float32 ray
+// parameter for the element sizes met in practice.
+constexpr float kGrazingCos2 = 1.0f / 4096.0f;
+
+// D = v - Q for the ray point Q = M + s d, formed from the exact pairs:
+// s d_hi = p + pe exactly (fused multiply-add residual), v - M_hi = t1 + t1e
+// exactly (two-sum), and the small terms pe + s d_lo + M_lo summed apart, so
+// that |D - (v - Q)| <= 3.1 u |D| + 28 u^2 R componentwise.
+__device__ __forceinline__ float3 offset_from_ray(const Ray& r, float s, float3 v) {
+  float3 p = make_float3(s * r.d.x, s * r.d.y, s * r.d.z);
+  float3 pe = make_float3(fmaf(s, r.d.x, -p.x), fmaf(s, r.d.y, -p.y), fmaf(s, r.d.z, -p.z));
+  float3 rho = make_float3((pe.x + s * r.dlo.x) + r.Mlo.x, (pe.y + s * r.dlo.y) + r.Mlo.y,
+                           (pe.z + s * r.dlo.z) + r.Mlo.z);
+  float3 t1, t1e;
+  two_sum_f(v.x, -r.M.x, t1.x, t1e.x);
+  two_sum_f(v.y, -r.M.y, t1.y, t1e.y);
+  two_sum_f(v.z, -r.M.z, t1.z, t1e.z);
+  return make_float3((t1.x - p.x) + (t1e.x - rho.x), (t1.y - p.y) + (t1e.y - rho.y),
+                     (t1.z - p.z) + (t1e.z - rho.z));
+}
+
+// Walk filter.  With w = fl(d_hi x D) and e = fl(a - v), the exact edge value
+// E(v, a) = (a - v) . (d x (v - S)) = (a - v) . (d x (v - Q)) differs from
+// fl(e . w) by at most |e|_1 |d|_inf (20.5 u |D|_inf + 57.2 u^2 R): six
+// roundings per monomial of e.(d_hi x D), the d_lo x D term, and the error of
+// D itself.  The constants below (24 u, 64 u^2) leave room for the rounding of
+// the bound's own evaluation.
+constexpr float kWalkRel = 24.0f * 5.9604644775390625e-8f;
 
 __device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, LaneStats& st) {
   if (fast != 2) return fast;
@@ -131,6 +188,12 @@ __device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 
 __device__ __forceinline__ int fast_sign(float3 e, float3 w, float3 W) {
   float E = e.x * w.x + e.y * w.y + e.z * w.z;
   float B = kFilterRel * (fabsf(e.x) * W.x + fabsf(e.y) * W.y + fabsf(e.z) * W.z) + kFilterAbs;
+  return E > B ? 1 : (E < -B ? -1 : 2);
+}
+
+__device__ __forceinline__ int walk_sign(float3 e, float3 w, float K) {
+  float E = e.x * w.x + e.y * w.y + e.z * w.z;
+  float B = (fabsf(e.x) + fabsf(e.y) + fabsf(e.z)) * K + kFilterAbs;
   return E > B ? 1 : (E < -B ? -1 : 2);
 }
 
@@ -283,12 +346,12 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
   float3 a1 = make_float3(q1.x, q1.y, q1.z);
   float3 a2 = make_float3(q2.x, q2.y, q2.z);
   float3 v = make_float3(q3.x, q3.y, q3.z);
-  // Ray parameters are kept as s = t - 1/2 around the reference point M, and
-  // each segment is measured from the current entry point Q = M + s_in d, a
-  // point within one tetrahedron of the exit face, so the float32 rounding of
-  // (v - Q) . n stays proportional to the element size rather than to the
-  // source distance.  Only segment lengths are accumulated, never
-  // differences of rounded parameters.
+  // Ray parameters are kept as s = t - 1/2 around the reference point M.  Each
+  // step forms D = v - Q for the current entry point Q = M + s_in d from the
+  // exact pairs (offset_from_ray), so both the exit-face signs and the
+  // crossing are evaluated from a vector of element size whose error is a
+  // few ulps of itself, not of the source distance.  Only segment lengths
+  // are accumulated, never differences of rounded parameters.
   float s_in = (float)crossing_s_fp64(r.S, r.P, a0, a1, a2);
   s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
   float xcur = 0.f;
@@ -299,12 +362,13 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
       st.failed++;
       break;
     }
-    float3 w, W;
-    cross_pair(r, v, w, W);
+    float3 D = offset_from_ray(r, s_in, v);
+    float3 w = f3cross(r.d, D);
+    float K = r.dinf * (kWalkRel * fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))) + r.kR);
     float3 e0 = f3sub(a0, v), e1 = f3sub(a1, v), e2 = f3sub(a2, v);
-    int s0 = fast_sign(e0, w, W);
-    int s1 = fast_sign(e1, w, W);
-    int s2 = fast_sign(e2, w, W);
+    int s0 = walk_sign(e0, w, K);
+    int s1 = walk_sign(e1, w, K);
+    int s2 = walk_sign(e2, w, K);
     if (s0 == 2) s0 = resolve(2, r, v, a0, st);
     if (s1 == 2) s1 = resolve(2, r, v, a1, st);
     if (s2 == 2) s2 = resolve(2, r, v, a2, st);
@@ -330,8 +394,7 @@ __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int en
     float den = f3dot(r.d, n);
     float dt;
     if (den * den >= kGrazingCos2 * r.dd * f3dot(n, n)) {
-      float3 Q = make_float3(r.M.x + s_in * r.d.x, r.M.y + s_in * r.d.y, r.M.z + s_in * r.d.z);
-      dt = f3dot(f3sub(v, Q), n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
+      dt = f3dot(D, n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
     } else {
       st.grazing++;
       float3 ai = k == 2 ? a0 : (k == 0 ? a1 : a2);
@@ -468,7 +531,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     }
     if (active) {
       int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
-      Ray r = cone_ray(G, a, i, j);
+      Ray r = cone_ray(G, M.extent, a, i, j);
       int e = io.entry ? io.entry[rid] : find_entry(M, r, st);
       WalkOut<MODE> o;
       o.xhat = io.out_f32;
@@ -488,7 +551,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
   } else if (active) {
     int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
     int64_t rid0 = (int64_t)a0 * G.nv * G.nu;
-    Ray r = cone_ray(G, a, i, j);
+    Ray r = cone_ray(G, M.extent, a, i, j);
     int e = (io.entry && MODE != kModeEntry) ? io.entry[rid] : find_entry(M, r, st);
     if constexpr (MODE == kModeEntry) {
       io.out_i32[rid] = e;
@@ -595,13 +658,13 @@ __global__ __launch_bounds__(256) void list_walk_kernel(MeshView M, GeomView G, 
       int i = (int)(rid % G.nu);
       int j = (int)((rid / G.nu) % G.nv);
       int a = (int)(rid / ((int64_t)G.nu * G.nv));
-      r = cone_ray(G, a, i, j);
+      r = cone_ray(G, M.extent, a, i, j);
     } else {
       r.S = make_float3(S[3 * k], S[3 * k + 1], S[3 * k + 2]);
       r.P = make_float3(P[3 * k], P[3 * k + 1], P[3 * k + 2]);
       r.U = make_float3(U[3 * k], U[3 * k + 1], U[3 * k + 2]);
       r.V = make_float3(V[3 * k], V[3 * k + 1], V[3 * k + 2]);
-      finish_ray(r);
+      finish_ray(r, M.extent);
     }
     // {P - S, U, V} must be a basis for the tie-breaking translation.
     float s3[3] = {r.S.x, r.S.y, r.S.z}, p3[3] = {r.P.x, r.P.y, r.P.z}, u3[3] = {r.U.x, r.U.y, r.U.z},

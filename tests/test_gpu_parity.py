@@ -89,14 +89,19 @@ def ray_lengths(c, ids):
 
 def compare_traces(gpu, ref, dlen):
     assert len(gpu) == len(ref)
+    worst = 0.0
     for k, ((gt, gl), (rt, rl)) in enumerate(zip(gpu, ref)):
         assert np.array_equal(gt, rt), f"ray {k}: sequences differ\n gpu {gt[:40]}\n ref {rt[:40]}"
         chord = float(rl.sum())
         err = np.abs(gl.astype(np.float64) - rl)
         i = int(np.argmax(err)) if len(err) else 0
-        assert np.all(err <= 1e-5 * max(chord, dlen[k] / 64)), (
+        tol = 1e-5 * max(chord, dlen[k] / 64)
+        assert np.all(err <= tol), (
             f"ray {k}: lengths; chord {chord:.6e} n {len(rl)} worst seg {i} gpu {gl[i]:.9e} ref {rl[i]:.9e} "
             f"err {err[i]:.3e}; all gpu {gl[:8]} ref {rl[:8]}")
+        if len(err):
+            worst = max(worst, float(err.max()) / tol)
+    print(f"segment lengths: worst err/tol {worst:.3f} over {len(gpu)} rays")
 
 
 def forward_tolerance(c, x, ids=None):
@@ -118,6 +123,7 @@ def assert_within(got, ref, tol, what):
         k = int(np.argmax(err / np.maximum(tol, 1e-300)))
         raise AssertionError(f"{what}: {int(bad.sum())} of {bad.size} out of tolerance; worst index {k}: "
                              f"got {got[k]!r} ref {ref[k]!r} err {err[k]:.3e} tol {tol[k]:.3e}")
+    print(f"{what}: worst err/tol {float(np.max(err / np.maximum(tol, 1e-300))) if err.size else 0.0:.3f}")
 
 
 def check_stats(mesh):
