@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--gather", action="store_true")
+    ap.add_argument("--bp", default="atomic", choices=["atomic", "shadow", "atomic_direct", "gather"],
+                    help="backprojection of the timed step")
     ap.add_argument("--json-extra", default=None)
     ap.add_argument("--batch-cgls", type=int, default=0, metavar="NPROB",
                     help="instead of the default line: batched (one persistent launch per direction, graph-replayed) "
@@ -220,7 +222,7 @@ def main():
         P.entry = entry
         P.forward(x, out=proj)
         e2.record(s)
-        P.backproject(proj, mode="atomic", out=xhat)
+        P.backproject(proj, mode=args.bp, out=xhat)
         e3.record(s)
         if record:
             ev["entry"].append((e0, e1))
@@ -246,10 +248,14 @@ def main():
     value = segs_total / elapsed
     fwd_gbs = FWD_BYTES_PER_SEG * segs_per_walk / (ms["forward"] * 1e-3) / 1e9
     bwd_gbs = BWD_BYTES_PER_SEG * segs_per_walk / (ms["backproject"] * 1e-3) / 1e9
+    bp_kernel = {"atomic": "atomic backprojection walk (pixel_walk_kernel<2>)",
+                 "atomic_direct": "direct-atomic backprojection walk (pixel_walk_kernel<2>)",
+                 "gather": "gather backprojection (walk fill + sort + segment sum)",
+                 "shadow": "element-driven backprojection (shadow_backproject_kernel)"}[args.bp]
     if ms["forward"] >= ms["backproject"]:
         dom, ach, bps = "forward walk (pixel_walk_kernel<1>)", fwd_gbs, FWD_BYTES_PER_SEG
     else:
-        dom, ach, bps = "atomic backprojection walk (pixel_walk_kernel<2>)", bwd_gbs, BWD_BYTES_PER_SEG
+        dom, ach, bps = bp_kernel, bwd_gbs, BWD_BYTES_PER_SEG
     out = {
         "metric": "tet-segments/s fwd+back at 1 GPU",
         "value": value,
@@ -270,7 +276,7 @@ def main():
             "detector": [w.cone.nv, w.cone.nu],
             "angles": len(w.angles),
             "segments_per_walk": segs_per_walk,
-            "step": "entry search + forward + atomic backprojection",
+            "step": f"entry search + forward + {args.bp} backprojection",
         },
         "roofline": {
             "bound": "hbm",
@@ -287,7 +293,10 @@ def main():
         "ingest_s": ingest_s,
     }
     # The other backprojection variants, one timed call each (not part of the step).
-    for mode in ("atomic_direct",) + (("gather",) if args.gather else ()):
+    others = [m for m in ("atomic", "shadow", "atomic_direct") if m != args.bp]
+    if args.gather and args.bp != "gather":
+        others.append("gather")
+    for mode in others:
         torch.cuda.synchronize()
         g0 = torch.cuda.Event(enable_timing=True)
         g1 = torch.cuda.Event(enable_timing=True)
@@ -296,18 +305,10 @@ def main():
         g1.record()
         torch.cuda.synchronize()
         t_ms = g0.elapsed_time(g1)
-        out.setdefault("variants", {})[mode] = {"ms": t_ms, "seg_per_s": segs_per_walk / (t_ms * 1e-3)}
+        out.setdefault("variants", {})[mode] = {"ms": t_ms, "seg_per_s": segs_per_walk / (t_ms * 1e-3),
+                                                "hbm_frac": BWD_BYTES_PER_SEG * segs_per_walk / (t_ms * 1e-3)
+                                                / 1e9 / HBM_PEAK_GBS}
     mesh.stats(reset=True)
-    if False:
-        torch.cuda.synchronize()
-        g0 = torch.cuda.Event(enable_timing=True)
-        g1 = torch.cuda.Event(enable_timing=True)
-        g0.record()
-        P.backproject(proj, mode="gather", out=xhat)
-        g1.record()
-        torch.cuda.synchronize()
-        out["gather_ms"] = g0.elapsed_time(g1)
-        out["gather_seg_per_s"] = segs_per_walk / (out["gather_ms"] * 1e-3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     if args.json_extra:

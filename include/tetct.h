@@ -172,14 +172,20 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
                                   distinct tetrahedron to xhat */
 #define TCT_BP_GATHER 1        /* deterministic: per-tetrahedron lists of (ray, length), summed in ray order */
 #define TCT_BP_ATOMIC_DIRECT 2 /* one float32 atomic add to xhat per segment, as in the paper */
+#define TCT_BP_SHADOW 3        /* deterministic, element-driven: each tetrahedron enumerates the pixels of
+                                  its detector shadow per angle, keeps the rays that cross it (the walk's
+                                  exact predicate) and sums length x y_j in ray order in float64 */
 
 /* Backprojection xhat_i = sum_j a_ij y_j (Eq. 3 with the detector index on y).
  *   proj  device float [na][nv][nu]
  *   xhat  device float [nt], internal order; overwritten unless accumulate != 0
- *   mode  TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT or TCT_BP_GATHER.  The atomic modes
- *         sum in a run-dependent order.  GATHER gives bitwise-identical results
- *         run to run; it allocates stream-ordered scratch and synchronises the
- *         stream once per angle chunk. */
+ *   mode  TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_GATHER or TCT_BP_SHADOW.
+ *         The atomic modes sum in a run-dependent order.  GATHER and SHADOW give
+ *         bitwise-identical results run to run.  GATHER allocates stream-ordered
+ *         scratch and synchronises the stream once per angle chunk; SHADOW does
+ *         not use `entry`, never synchronises, and allocates stream-ordered
+ *         float64 partial sums only when the mesh has too few elements to fill
+ *         the device (then angles are split into chunks summed in order). */
 tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
                            int accumulate, const int32_t* entry, tct_stream s);
 

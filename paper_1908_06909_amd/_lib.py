@@ -31,6 +31,7 @@ TCT_MESH_HOST_ONLY = 2
 TCT_BP_ATOMIC = 0
 TCT_BP_GATHER = 1
 TCT_BP_ATOMIC_DIRECT = 2
+TCT_BP_SHADOW = 3
 TCT_DOT_WORKSPACE = 512
 TCT_VECSET_DOT_WORKSPACE = 256
 

@@ -48,6 +48,10 @@ struct MeshView {
   int nb;
   unsigned long long* counters;  // tct_stats fields, int64 each
   float extent;                  // largest |coordinate| of any node
+  // tetxyz[3 t + 0..2]: the four vertices of tetrahedron t as 12 floats
+  // (v0.xyz v1.xyz v2.xyz v3.xyz), ordered so that
+  // det[v1 - v0, v2 - v0, v3 - v0] > 0.
+  const float4* tetxyz;
 };
 
 // Cone-beam frames: frame[12 a + 0..11] = S, D, U, V of angle a.
@@ -93,6 +97,7 @@ struct tct_mesh {
   float lo[3], hi[3];              // bounding box of the nodes
   float4* d_faces = nullptr;
   float4* d_bfaces = nullptr;
+  float4* d_tetxyz = nullptr;
   tct::BvhNode* d_bvh = nullptr;
   int32_t* d_perm = nullptr;
   int32_t* d_inv_perm = nullptr;
@@ -108,6 +113,7 @@ struct tct_mesh {
     v.nt = nt;
     v.nb = nb;
     v.counters = d_counters;
+    v.tetxyz = d_tetxyz;
     v.extent = 0.f;
     for (int k = 0; k < 3; ++k) v.extent = std::max(v.extent, std::max(std::fabs(lo[k]), std::fabs(hi[k])));
     return v;

@@ -370,6 +370,18 @@ tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32
     const float* o = P(Ts[4 * (size_t)t + f]);
     bfaces[4 * (size_t)j + 3] = make_float4(o[0], o[1], o[2], 0.f);
   }
+  // Vertex coordinates per tetrahedron for the element-driven kernels, in
+  // positive orientation (v2 and v3 swapped when the sorted order is negative).
+  std::vector<float4> tetxyz(3 * (size_t)nt);
+  for (int i = 0; i < nt; ++i) {
+    const int32_t* q = &Ts[4 * (size_t)m->perm[i]];
+    int idx[4] = {q[0], q[1], q[2], q[3]};
+    if (orient3d_sign(P(idx[0]), P(idx[1]), P(idx[2]), P(idx[3])) < 0) std::swap(idx[2], idx[3]);
+    float c[12];
+    for (int k = 0; k < 4; ++k)
+      for (int x = 0; x < 3; ++x) c[3 * k + x] = P(idx[k])[x];
+    for (int w = 0; w < 3; ++w) tetxyz[3 * (size_t)i + w] = make_float4(c[4 * w], c[4 * w + 1], c[4 * w + 2], c[4 * w + 3]);
+  }
   tct_status st;
   auto fail = [&](tct_status s) {
     mesh_free_device(m);
@@ -383,6 +395,7 @@ tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32
   }
   if ((st = upload(faces, &m->d_faces, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(bfaces, &m->d_bfaces, &m->device_bytes)) != TCT_OK) return fail(st);
+  if ((st = upload(tetxyz, &m->d_tetxyz, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(nodes, &m->d_bvh, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(m->perm, &m->d_perm, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(m->inv_perm, &m->d_inv_perm, &m->device_bytes)) != TCT_OK) return fail(st);
@@ -396,12 +409,14 @@ void mesh_free_device(tct_mesh* m) {
   if (!m) return;
   if (m->d_faces) (void)hipFree(m->d_faces);
   if (m->d_bfaces) (void)hipFree(m->d_bfaces);
+  if (m->d_tetxyz) (void)hipFree(m->d_tetxyz);
   if (m->d_bvh) (void)hipFree(m->d_bvh);
   if (m->d_perm) (void)hipFree(m->d_perm);
   if (m->d_inv_perm) (void)hipFree(m->d_inv_perm);
   if (m->d_counters) (void)hipFree(m->d_counters);
   m->d_faces = nullptr;
   m->d_bfaces = nullptr;
+  m->d_tetxyz = nullptr;
   m->d_bvh = nullptr;
   m->d_perm = m->d_inv_perm = nullptr;
   m->d_counters = nullptr;

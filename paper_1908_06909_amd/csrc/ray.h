@@ -1,0 +1,52 @@
+// Device helpers shared by the ray walk and the element-driven
+// backprojection: small vector operations, the pixel ray endpoint and the
+// exact perturbed edge sign.  Both kernels must see identical rays and
+// identical signs, so they take them from here.
+#pragma once
+
+#include "common.h"
+#include "exact.h"
+
+namespace tct {
+namespace {
+
+__device__ __forceinline__ float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ float f3dot(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ float3 f3cross(float3 a, float3 b) {
+  return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ float3 f3abs(float3 a) { return make_float3(fabsf(a.x), fabsf(a.y), fabsf(a.z)); }
+__device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.y, a.z, a.w); }
+
+// Knuth's two-sum: a + b = s + e exactly (round to nearest, no overflow).
+__device__ __forceinline__ void two_sum_f(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bv = s - a;
+  float av = s - bv;
+  e = (a - av) + (b - bv);
+}
+
+// Detector point of pixel (u, v) for one angle's frame f = {S, D, U, V}:
+// P = fl(fl(D + fl(u U)) + fl(v V)) per component, with no contraction, so
+// that every kernel forms bit-identical rays (one ray per detector pixel
+// centre, Section II-A).
+__device__ __forceinline__ float3 pixel_point(const float* f, float u, float v) {
+  float3 P;
+  P.x = __fadd_rn(__fadd_rn(f[3], __fmul_rn(u, f[6])), __fmul_rn(v, f[9]));
+  P.y = __fadd_rn(__fadd_rn(f[4], __fmul_rn(u, f[7])), __fmul_rn(v, f[10]));
+  P.z = __fadd_rn(__fadd_rn(f[5], __fmul_rn(u, f[8])), __fmul_rn(v, f[11]));
+  return P;
+}
+
+// Exact perturbed sign of the edge (p, q): returns sign + 1 in bits 0-1 and
+// the exact.h flags in bits 2-3.
+__device__ __noinline__ int slow_edge_sign(float3 S, float3 P, float3 U, float3 V, float3 p, float3 q) {
+  float s[3] = {S.x, S.y, S.z}, pp[3] = {P.x, P.y, P.z}, u[3] = {U.x, U.y, U.z}, v[3] = {V.x, V.y, V.z};
+  float a[3] = {p.x, p.y, p.z}, b[3] = {q.x, q.y, q.z};
+  unsigned flags = 0;
+  int sg = perturbed_edge_sign(s, pp, u, v, a, b, &flags);
+  return (sg + 1) | (int)(flags << 2);
+}
+
+}  // namespace
+}  // namespace tct

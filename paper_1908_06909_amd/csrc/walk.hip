@@ -31,6 +31,7 @@
 #include "common.h"
 #include "exact.h"
 #include "kernels.h"
+#include "ray.h"
 
 namespace tct {
 
@@ -61,22 +62,6 @@ struct LaneStats {
   int steps = 0, zero = 0, fp64 = 0, exact = 0, pert = 0, failed = 0, grazing = 0;
 };
 
-__device__ __forceinline__ float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
-__device__ __forceinline__ float f3dot(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ float3 f3cross(float3 a, float3 b) {
-  return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ float3 f3abs(float3 a) { return make_float3(fabsf(a.x), fabsf(a.y), fabsf(a.z)); }
-__device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.y, a.z, a.w); }
-
-// Knuth's two-sum: a + b = s + e exactly (round to nearest, no overflow).
-__device__ __forceinline__ void two_sum_f(float a, float b, float& s, float& e) {
-  s = a + b;
-  float bv = s - a;
-  float av = s - bv;
-  e = (a - av) + (b - bv);
-}
-
 // The ray is carried with an exact direction d = d_hi + d_lo and an almost
 // exact point M = M_hi + M_lo at t = 1/2 (error O(u^2 |M|)), so positions on
 // it near the mesh can be formed to a relative accuracy set by their distance
@@ -102,7 +87,7 @@ __device__ __forceinline__ void finish_ray(Ray& r, float mesh_extent) {
   r.kR = 64.0f * 3.552713678800501e-15f * R;  // 64 u^2 R with u = 2^-24
 }
 
-// Pixel ray: P = fl(fl(D + fl(u U)) + fl(v V)) per component, no contraction.
+// Pixel ray S -> P(u, v) of one angle's frame.
 __device__ __forceinline__ Ray cone_ray(const GeomView& g, float mesh_extent, int a, int i, int j) {
   const float* f = g.frame + 12 * a;
   float u = g.ut[i], v = g.vt[j];
@@ -110,21 +95,9 @@ __device__ __forceinline__ Ray cone_ray(const GeomView& g, float mesh_extent, in
   r.S = make_float3(f[0], f[1], f[2]);
   r.U = make_float3(f[6], f[7], f[8]);
   r.V = make_float3(f[9], f[10], f[11]);
-  r.P.x = __fadd_rn(__fadd_rn(f[3], __fmul_rn(u, f[6])), __fmul_rn(v, f[9]));
-  r.P.y = __fadd_rn(__fadd_rn(f[4], __fmul_rn(u, f[7])), __fmul_rn(v, f[10]));
-  r.P.z = __fadd_rn(__fadd_rn(f[5], __fmul_rn(u, f[8])), __fmul_rn(v, f[11]));
+  r.P = pixel_point(f, u, v);
   finish_ray(r, mesh_extent);
   return r;
-}
-
-// Exact perturbed sign of the edge (p, q): returns sign + 1 in bits 0-1 and
-// the exact.h flags in bits 2-3.
-__device__ __noinline__ int slow_edge_sign(float3 S, float3 P, float3 U, float3 V, float3 p, float3 q) {
-  float s[3] = {S.x, S.y, S.z}, pp[3] = {P.x, P.y, P.z}, u[3] = {U.x, U.y, U.z}, v[3] = {V.x, V.y, V.z};
-  float a[3] = {p.x, p.y, p.z}, b[3] = {q.x, q.y, q.z};
-  unsigned flags = 0;
-  int sg = perturbed_edge_sign(s, pp, u, v, a, b, &flags);
-  return (sg + 1) | (int)(flags << 2);
 }
 
 // Ray parameter s = t - 1/2 where S + t (P - S) meets the plane through

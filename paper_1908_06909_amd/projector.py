@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_GATHER, call, lib, tct_cone, tct_stats
+from ._lib import TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_GATHER, TCT_BP_SHADOW, call, lib, tct_cone, tct_stats
 
 
 def _stream(device) -> int:
@@ -181,7 +181,8 @@ class Projector:
 
     def backproject(self, y: torch.Tensor, mode: str = "atomic", out: Optional[torch.Tensor] = None,
                     accumulate: bool = False, use_cache: bool = True) -> torch.Tensor:
-        m = {"atomic": TCT_BP_ATOMIC, "atomic_direct": TCT_BP_ATOMIC_DIRECT, "gather": TCT_BP_GATHER}[mode]
+        m = {"atomic": TCT_BP_ATOMIC, "atomic_direct": TCT_BP_ATOMIC_DIRECT, "gather": TCT_BP_GATHER,
+             "shadow": TCT_BP_SHADOW}[mode]
         if out is None:
             out = torch.empty(self.nt, dtype=torch.float32, device=self.device)
             accumulate = False

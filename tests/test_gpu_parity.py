@@ -170,7 +170,7 @@ def _bp_tolerance(c, y):
     return 1e-5 * chord_w + nterm * 2.0 ** -24 * absbp + 1e-30
 
 
-@pytest.mark.parametrize("mode", ["atomic", "atomic_direct", "gather"])
+@pytest.mark.parametrize("mode", ["atomic", "atomic_direct", "gather", "shadow"])
 def test_cfg0_backproject(mode):
     c = case("cfg0")
     rng = np.random.default_rng(31)
@@ -198,6 +198,20 @@ def test_cfg0_gather_is_deterministic_and_accumulates():
     assert np.allclose(acc2, acc, rtol=1e-5, atol=1e-5)
 
 
+def test_cfg0_shadow_is_deterministic_and_accumulates():
+    c = case("cfg0")
+    rng = np.random.default_rng(34)
+    yt = torch.as_tensor(rng.uniform(-1, 1, c.orc.nrays).astype(f32), device=DEV)
+    a = c.P.backproject(yt, mode="shadow").cpu().numpy()
+    b = c.P.backproject(yt, mode="shadow").cpu().numpy()
+    assert np.array_equal(a.view(np.int32), b.view(np.int32))
+    base = torch.full((c.orc.nt,), 0.25, dtype=torch.float32, device=DEV)
+    acc = c.P.backproject(yt, mode="shadow", out=base.clone(), accumulate=True).cpu().numpy()
+    assert np.allclose(acc, a + np.float32(0.25), rtol=0, atol=1e-6)
+    g = c.P.backproject(yt, mode="gather").cpu().numpy()
+    assert np.allclose(a, g, rtol=1e-5, atol=1e-5)
+
+
 def test_cfg0_adjoint():
     c = case("cfg0")
     rng = np.random.default_rng(33)
@@ -205,7 +219,7 @@ def test_cfg0_adjoint():
     y = rng.uniform(-1, 1, c.orc.nrays).astype(f32)
     xi = c.x_internal(x)
     Ax = c.P.forward(xi).cpu().numpy().ravel().astype(np.float64)
-    for mode in ("atomic", "atomic_direct", "gather"):
+    for mode in ("atomic", "atomic_direct", "gather", "shadow"):
         Aty = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode)).astype(np.float64)
         lhs = float(np.dot(Ax, y))
         rhs = float(np.dot(x.astype(np.float64), Aty))
@@ -291,6 +305,14 @@ def test_graded_small_all_sequences():
     assert_within(got, ref, forward_tolerance(c, c.w.x), "graded forward")
     st = check_stats(c.mesh)
     assert st["perturbed_ties"] > 0
+    # Rays through vertices and along edges: the element-driven backprojection
+    # must pick the same tetrahedra as the walk (same perturbed predicate).
+    y = np.random.default_rng(4).uniform(-1, 1, c.orc.nrays).astype(f32)
+    ref = c.orc.backproject(y)
+    got = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode="shadow")).astype(np.float64)
+    assert_within(got, ref, _bp_tolerance(c, y), "graded shadow backprojection")
+    st = check_stats(c.mesh)
+    assert st["perturbed_ties"] > 0
 
 
 def test_cfg2_sampled_sequences_and_forward():
@@ -334,9 +356,53 @@ def test_ragged_detector_and_missing_rays():
     assert np.all(got[ref == 0] == 0)
     assert_within(got, ref, forward_tolerance(c, c.w.x), "ragged forward")
     y = np.random.default_rng(3).uniform(0, 1, c.orc.nrays).astype(f32)
-    bp = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode="gather"))
-    assert np.linalg.norm(bp - c.orc.backproject(y)) <= 1e-5 * np.linalg.norm(c.orc.backproject(y))
+    ref_bp = c.orc.backproject(y)
+    for mode in ("gather", "shadow"):
+        bp = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode))
+        assert np.linalg.norm(bp - ref_bp) <= 1e-5 * np.linalg.norm(ref_bp), mode
+    assert_within(bp.astype(np.float64), ref_bp, _bp_tolerance(c, y), "ragged shadow backprojection")
     check_stats(c.mesh)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_full_size_shadow_adjoint_and_atomic_agreement(name):
+    """Full-size element-driven backprojection, in the launch the benchmark
+    times: adjoint identity against the (oracle-checked) forward projection,
+    and agreement with the ray-driven scatter element by element."""
+    c = case(name)
+    rng = np.random.default_rng(5)
+    x = c.w.x.astype(f32)
+    xi = c.x_internal(x)
+    Ax = c.P.forward(xi).reshape(-1)
+    y = torch.as_tensor(rng.uniform(0, 1, c.geom.nrays).astype(f32), device=DEV)
+    sh = c.P.backproject(y, mode="shadow")
+    sh2 = c.P.backproject(y, mode="shadow")
+    assert torch.equal(sh, sh2)
+    at = c.P.backproject(y, mode="atomic")
+    lhs = float(torch.dot(Ax.double(), y.double()))
+    rhs = float(torch.dot(xi.double(), sh.double()))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
+    # The scatter sums ~10^4 float32 terms per element in a run-dependent
+    # order, so the bar here is its own rounding, not the oracle's.
+    err = (sh.double() - at.double()).abs()
+    assert float(err.max()) <= 2e-4 * float(at.double().abs().max()), float(err.max())
+    assert float(err.norm()) <= 2e-5 * float(at.double().norm())
+    check_stats(c.mesh)
+
+
+def test_shadow_range_launches_sum_to_full():
+    from paper_1908_06909_amd._lib import TCT_BP_SHADOW, call, tct_range
+    import ctypes
+    c = case("graded_small")
+    y = torch.as_tensor(np.random.default_rng(6).uniform(0, 1, c.orc.nrays).astype(f32), device=DEV)
+    full = c.P.backproject(y, mode="shadow")
+    acc = torch.zeros_like(full)
+    s = torch.cuda.current_stream().cuda_stream
+    na = c.geom.na
+    for a0, cnt in ((0, 5), (5, 1), (6, na - 6)):
+        call("tct_backproject_range", c.mesh.handle, c.geom.handle, y.data_ptr(), acc.data_ptr(), TCT_BP_SHADOW, 1,
+             None, ctypes.byref(tct_range(a0, cnt, 8)), s)
+    assert torch.allclose(acc, full, rtol=1e-6, atol=1e-6)
 
 
 def test_geometry_rejected_when_mesh_not_between_source_and_detector():
