@@ -13,6 +13,7 @@ enum WalkMode {
   kModeCountPos = 4,
   kModeTrace = 5,
   kModeGatherFill = 6,
+  kModeBackDirect = 7,  // backprojection with one global atomic per segment
 };
 
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,

@@ -261,14 +261,21 @@ __device__ __forceinline__ unsigned remap_local(unsigned p, unsigned f, unsigned
 // 16 x 16 block spans about two elements), so scattering every segment with a
 // global atomic makes dozens of lanes update one address at once.  Instead
 // each block sums its segments per tetrahedron in an LDS open-addressing
-// table (key = tetrahedron, linear probing) and flushes one global atomic per
-// distinct tetrahedron at the end; a segment that finds no slot within
+// table (key = tetrahedron, linear probing) and adds one global atomic per
+// distinct tetrahedron when it flushes the table.  A 16 x 16 bundle crosses
+// some 4000 tetrahedra on its way through the benchmark mesh, more than the
+// table holds, so the rays advance in windows of kLdsWindow steps and the
+// table is flushed after each window: it only holds the tetrahedra one
+// window of the bundle touches.  A segment that finds no slot within
 // kLdsProbes probes goes straight to global memory.
-constexpr int kLdsSlots = 2048;
+constexpr int kLdsSlots = 4096;
+constexpr int kLdsHashShift = 20;  // multiplicative hash keeps the top 12 bits
+static_assert(kLdsSlots == (1 << (32 - kLdsHashShift)), "hash width must match the table size");
 constexpr int kLdsProbes = 8;
+constexpr int kLdsWindow = 64;
 
 __device__ __forceinline__ void lds_accumulate(int* keys, float* vals, int tet, float v, float* xhat) {
-  unsigned h = ((unsigned)tet * 2654435761u) >> 21;  // 11-bit multiplicative hash
+  unsigned h = ((unsigned)tet * 2654435761u) >> kLdsHashShift;
 #pragma unroll 1
   for (int p = 0; p < kLdsProbes; ++p) {
     unsigned slot = (h + p) & (kLdsSlots - 1);
@@ -305,128 +312,161 @@ struct WalkOut {
   int64_t count = 0;
 };
 
-// Walk one ray from boundary face `entry` to the boundary.
+// Walk state between steps: the entry face as three vertex slots (local
+// indices packed in `loc`), the fourth vertex v (local index `locv`), the
+// current tetrahedron and the ray parameter where the ray entered it.
+struct WalkState {
+  float3 a0, a1, a2, v;
+  int tet;
+  unsigned loc, locv;
+  float s_in;
+  float xcur;  // forward projection: x of the current tetrahedron
+  int steps;
+};
+
+// Enter the mesh through boundary face `entry`.
 template <int MODE>
-__device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int entry, WalkOut<MODE>& o,
-                                         LaneStats& st) {
+__device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, int entry, WalkState& w,
+                                           const WalkOut<MODE>& o) {
   const float4* bq = M.bfaces + 4 * (size_t)entry;
   float4 q0 = bq[0], q1 = bq[1], q2 = bq[2], q3 = bq[3];
-  int tet = __float_as_int(q0.w);
+  w.tet = __float_as_int(q0.w);
   unsigned lp = (unsigned)__float_as_int(q1.w);
-  unsigned loc = lp & 63u;          // local index of slot s in bits 2s..2s+1
-  unsigned locv = (lp >> 6) & 3u;   // local index of v
-  float3 a0 = make_float3(q0.x, q0.y, q0.z);
-  float3 a1 = make_float3(q1.x, q1.y, q1.z);
-  float3 a2 = make_float3(q2.x, q2.y, q2.z);
-  float3 v = make_float3(q3.x, q3.y, q3.z);
+  w.loc = lp & 63u;          // local index of slot s in bits 2s..2s+1
+  w.locv = (lp >> 6) & 3u;   // local index of v
+  w.a0 = make_float3(q0.x, q0.y, q0.z);
+  w.a1 = make_float3(q1.x, q1.y, q1.z);
+  w.a2 = make_float3(q2.x, q2.y, q2.z);
+  w.v = make_float3(q3.x, q3.y, q3.z);
   // Ray parameters are kept as s = t - 1/2 around the reference point M.  Each
   // step forms D = v - Q for the current entry point Q = M + s_in d from the
   // exact pairs (offset_from_ray), so both the exit-face signs and the
   // crossing are evaluated from a vector of element size whose error is a
   // few ulps of itself, not of the source distance.  Only segment lengths
   // are accumulated, never differences of rounded parameters.
-  float s_in = (float)crossing_s_fp64(r.S, r.P, a0, a1, a2);
-  s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
-  float xcur = 0.f;
-  if constexpr (MODE == kModeForward) xcur = o.x[tet];
-  const int cap = M.nt + 1;
-  for (int step = 0;; ++step) {
-    if (step >= cap) {
-      st.failed++;
-      break;
-    }
-    float3 D = offset_from_ray(r, s_in, v);
-    float3 w = f3cross(r.d, D);
-    float K = r.dinf * (kWalkRel * fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))) + r.kR);
-    float3 e0 = f3sub(a0, v), e1 = f3sub(a1, v), e2 = f3sub(a2, v);
-    int s0 = walk_sign(e0, w, K);
-    int s1 = walk_sign(e1, w, K);
-    int s2 = walk_sign(e2, w, K);
-    if (s0 == 2) s0 = resolve(2, r, v, a0, st);
-    if (s1 == 2) s1 = resolve(2, r, v, a1, st);
-    if (s2 == 2) s2 = resolve(2, r, v, a2, st);
-    int k;
-    float3 ei, ej;
-    if (s0 < 0 && s1 > 0) {
-      k = 2;
-      ei = e0;
-      ej = e1;
-    } else if (s1 < 0 && s2 > 0) {
-      k = 0;
-      ei = e1;
-      ej = e2;
-    } else if (s2 < 0 && s0 > 0) {
-      k = 1;
-      ei = e2;
-      ej = e0;
-    } else {
-      st.failed++;
-      break;
-    }
-    float3 n = f3cross(ei, ej);
-    float den = f3dot(r.d, n);
-    float dt;
-    if (den * den >= kGrazingCos2 * r.dd * f3dot(n, n)) {
-      dt = f3dot(D, n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
-    } else {
-      st.grazing++;
-      float3 ai = k == 2 ? a0 : (k == 0 ? a1 : a2);
-      float3 aj = k == 2 ? a1 : (k == 0 ? a2 : a0);
-      dt = (float)(crossing_s_fp64(r.S, r.P, v, ai, aj) - (double)s_in);
-    }
-    dt = fminf(fmaxf(dt, 0.0f), fmaxf(0.5f - s_in, 0.0f));
-    st.steps++;
-    if (dt == 0.f) st.zero++;
-    // Next tetrahedron across the exit face (local face index loc[k]).
-    unsigned f = (loc >> (2 * k)) & 3u;
-    float4 rec = M.faces[4 * (size_t)tet + f];
-    if constexpr (MODE == kModeForward) {
-      o.acc += (double)dt * (double)xcur;
-    } else if constexpr (MODE == kModeBackAtomic) {
-      if (dt > 0.f) {
-        if (o.lds_keys)
-          lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.xhat);
-        else
-          unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
-      }
-    } else if constexpr (MODE == kModeCountAll) {
-      o.count++;
-    } else if constexpr (MODE == kModeCountPos) {
-      if (dt > 0.f) o.count++;
-    } else if constexpr (MODE == kModeTrace) {
-      o.out_tet[o.cursor] = o.perm[tet];
-      o.out_len[o.cursor] = dt * r.dn;
+  float s_in = (float)crossing_s_fp64(r.S, r.P, w.a0, w.a1, w.a2);
+  w.s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
+  w.xcur = 0.f;
+  if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
+  w.steps = 0;
+}
+
+// One step: leave the current tetrahedron, apply the mode's action for its
+// segment, move to the neighbour.  Returns false once the ray has left the
+// mesh (or the walk failed).
+template <int MODE>
+__device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, WalkState& w, WalkOut<MODE>& o,
+                                          LaneStats& st) {
+  if (w.steps > M.nt) {
+    st.failed++;
+    return false;
+  }
+  w.steps++;
+  const float3 v = w.v;
+  float3 D = offset_from_ray(r, w.s_in, v);
+  float3 wv = f3cross(r.d, D);
+  float K = r.dinf * (kWalkRel * fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))) + r.kR);
+  float3 e0 = f3sub(w.a0, v), e1 = f3sub(w.a1, v), e2 = f3sub(w.a2, v);
+  int s0 = walk_sign(e0, wv, K);
+  int s1 = walk_sign(e1, wv, K);
+  int s2 = walk_sign(e2, wv, K);
+  if (s0 == 2) s0 = resolve(2, r, v, w.a0, st);
+  if (s1 == 2) s1 = resolve(2, r, v, w.a1, st);
+  if (s2 == 2) s2 = resolve(2, r, v, w.a2, st);
+  int k;
+  float3 ei, ej;
+  if (s0 < 0 && s1 > 0) {
+    k = 2;
+    ei = e0;
+    ej = e1;
+  } else if (s1 < 0 && s2 > 0) {
+    k = 0;
+    ei = e1;
+    ej = e2;
+  } else if (s2 < 0 && s0 > 0) {
+    k = 1;
+    ei = e2;
+    ej = e0;
+  } else {
+    st.failed++;
+    return false;
+  }
+  float3 n = f3cross(ei, ej);
+  float den = f3dot(r.d, n);
+  float dt;
+  if (den * den >= kGrazingCos2 * r.dd * f3dot(n, n)) {
+    dt = f3dot(D, n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
+  } else {
+    st.grazing++;
+    const bool k0 = k == 0, k2 = k == 2;
+    const float3 ai = make_float3(k2 ? w.a0.x : (k0 ? w.a1.x : w.a2.x), k2 ? w.a0.y : (k0 ? w.a1.y : w.a2.y),
+                                  k2 ? w.a0.z : (k0 ? w.a1.z : w.a2.z));
+    const float3 aj = make_float3(k2 ? w.a1.x : (k0 ? w.a2.x : w.a0.x), k2 ? w.a1.y : (k0 ? w.a2.y : w.a0.y),
+                                  k2 ? w.a1.z : (k0 ? w.a2.z : w.a0.z));
+    dt = (float)(crossing_s_fp64(r.S, r.P, v, ai, aj) - (double)w.s_in);
+  }
+  dt = fminf(fmaxf(dt, 0.0f), fmaxf(0.5f - w.s_in, 0.0f));
+  st.steps++;
+  if (dt == 0.f) st.zero++;
+  // Next tetrahedron across the exit face (local face index loc[k]).
+  const int tet = w.tet;
+  unsigned f = (w.loc >> (2 * k)) & 3u;
+  float4 rec = M.faces[4 * (size_t)tet + f];
+  if constexpr (MODE == kModeForward) {
+    o.acc += (double)dt * (double)w.xcur;
+  } else if constexpr (MODE == kModeBackAtomic) {
+    if (dt > 0.f) lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.xhat);
+  } else if constexpr (MODE == kModeBackDirect) {
+    if (dt > 0.f) unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
+  } else if constexpr (MODE == kModeCountAll) {
+    o.count++;
+  } else if constexpr (MODE == kModeCountPos) {
+    if (dt > 0.f) o.count++;
+  } else if constexpr (MODE == kModeTrace) {
+    o.out_tet[o.cursor] = o.perm[tet];
+    o.out_len[o.cursor] = dt * r.dn;
+    o.cursor++;
+  } else if constexpr (MODE == kModeGatherFill) {
+    if (dt > 0.f) {
+      o.out_tet[o.cursor] = tet;
+      o.out_len[o.cursor] = dt * o.weight;
       o.cursor++;
-    } else if constexpr (MODE == kModeGatherFill) {
-      if (dt > 0.f) {
-        o.out_tet[o.cursor] = tet;
-        o.out_len[o.cursor] = dt * o.weight;
-        o.cursor++;
-      }
     }
-    int packed = __float_as_int(rec.x);
-    if (packed < 0) break;
-    unsigned back = (unsigned)packed & 3u;
-    unsigned nl0 = remap_local((loc >> 0) & 3u, f, back);
-    unsigned nl1 = remap_local((loc >> 2) & 3u, f, back);
-    unsigned nl2 = remap_local((loc >> 4) & 3u, f, back);
-    unsigned nv_ = remap_local(locv, f, back);
-    if (k == 0) {
-      nl0 = nv_;
-      a0 = v;
-    } else if (k == 1) {
-      nl1 = nv_;
-      a1 = v;
-    } else {
-      nl2 = nv_;
-      a2 = v;
-    }
-    loc = nl0 | (nl1 << 2) | (nl2 << 4);
-    locv = back;
-    v = xyz(rec);
-    tet = packed >> 2;
-    s_in += dt;
-    if constexpr (MODE == kModeForward) xcur = o.x[tet];
+  }
+  // Keep the record one 16-byte load consumed here; otherwise the compiler
+  // splits it into four loads sunk into the next step, which serialises the
+  // dependent fetch behind the next step's arithmetic.
+  asm volatile("" : "+v"(rec.x), "+v"(rec.y), "+v"(rec.z), "+v"(rec.w));
+  int packed = __float_as_int(rec.x);
+  if (packed < 0) return false;
+  unsigned back = (unsigned)packed & 3u;
+  unsigned nl0 = remap_local((w.loc >> 0) & 3u, f, back);
+  unsigned nl1 = remap_local((w.loc >> 2) & 3u, f, back);
+  unsigned nl2 = remap_local((w.loc >> 4) & 3u, f, back);
+  unsigned nv_ = remap_local(w.locv, f, back);
+  // Slot k takes v (component-wise selects keep the slots in registers).
+  nl0 = k == 0 ? nv_ : nl0;
+  nl1 = k == 1 ? nv_ : nl1;
+  nl2 = k == 2 ? nv_ : nl2;
+  w.a0 = make_float3(k == 0 ? v.x : w.a0.x, k == 0 ? v.y : w.a0.y, k == 0 ? v.z : w.a0.z);
+  w.a1 = make_float3(k == 1 ? v.x : w.a1.x, k == 1 ? v.y : w.a1.y, k == 1 ? v.z : w.a1.z);
+  w.a2 = make_float3(k == 2 ? v.x : w.a2.x, k == 2 ? v.y : w.a2.y, k == 2 ? v.z : w.a2.z);
+  w.loc = nl0 | (nl1 << 2) | (nl2 << 4);
+  w.locv = back;
+  w.v = xyz(rec);
+  w.tet = packed >> 2;
+  w.s_in += dt;
+  if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
+  return true;
+}
+
+// Walk one ray from boundary face `entry` to the boundary.
+template <int MODE>
+__device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int entry, WalkOut<MODE>& o,
+                                         LaneStats& st) {
+  WalkState w;
+  walk_start<MODE>(M, r, entry, w, o);
+  while (walk_step<MODE>(M, r, w, o, st)) {
   }
 }
 
@@ -484,7 +524,8 @@ struct BlockIO {
 // Walk the rays of pixel block `block` (of angles [a0, a0 + na_chunk)).
 //   kModeEntry:      out_i32[rid] = entry face (or -1)
 //   kModeForward:    out_f32[rid] = sum_i a_ij x_i
-//   kModeBackAtomic: xhat[i] += a_ij y_j (through the LDS table when enabled)
+//   kModeBackAtomic: xhat[i] += a_ij y_j through the block's LDS table
+//   kModeBackDirect: xhat[i] += a_ij y_j, one global atomic per segment
 //   kModeCountPos:   counts[rid - rid0] = positive-length visits
 //   kModeGatherFill: keys/vals at offsets[rid - rid0]
 // Every thread of the block must call it (the backprojection synchronises).
@@ -495,31 +536,45 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
   bool active = tile_ray(G, tm, block, threadIdx.x, a0, na_chunk, &a, &i, &j);
   LaneStats st;
   if constexpr (MODE == kModeBackAtomic) {
-    if (io.lds_table) {
-      for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
-        tkeys[k] = -1;
-        tvals[k] = 0.f;
-      }
-      __syncthreads();
+    for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
+      tkeys[k] = -1;
+      tvals[k] = 0.f;
     }
+    __syncthreads();
+    Ray r;
+    WalkOut<MODE> o;
+    o.xhat = io.out_f32;
+    o.lds_keys = tkeys;
+    o.lds_vals = tvals;
+    WalkState w;
+    bool alive = false;
     if (active) {
       int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
-      Ray r = cone_ray(G, M.extent, a, i, j);
+      r = cone_ray(G, M.extent, a, i, j);
       int e = io.entry ? io.entry[rid] : find_entry(M, r, st);
-      WalkOut<MODE> o;
-      o.xhat = io.out_f32;
-      if (io.lds_table) {
-        o.lds_keys = tkeys;
-        o.lds_vals = tvals;
-      }
       o.weight = io.in[rid] * r.dn;
-      if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, e, o, st);
+      if (e >= 0 && o.weight != 0.f) {
+        walk_start<MODE>(M, r, e, w, o);
+        alive = true;
+      }
     }
-    if (io.lds_table) {
+    // The block's rays advance together in windows of kLdsWindow steps;
+    // after each window the table is added to xhat and cleared, so it only
+    // ever holds the tetrahedra of one window of the ray bundle.
+    for (;;) {
+#pragma unroll 1
+      for (int k = 0; k < kLdsWindow && alive; ++k) alive = walk_step<MODE>(M, r, w, o, st);
+      const int any = __syncthreads_or(alive ? 1 : 0);
+      for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
+        const int key = tkeys[k];
+        if (key >= 0) {
+          unsafeAtomicAdd(io.out_f32 + key, tvals[k]);
+          tkeys[k] = -1;
+          tvals[k] = 0.f;
+        }
+      }
       __syncthreads();
-      for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x)
-        if (tkeys[k] >= 0) unsafeAtomicAdd(io.out_f32 + tkeys[k], tvals[k]);
-      __syncthreads();
+      if (!any) break;
     }
   } else if (active) {
     int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
@@ -533,6 +588,11 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       o.x = io.in;
       if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
       io.out_f32[rid] = (float)(o.acc * (double)r.dn);
+    } else if constexpr (MODE == kModeBackDirect) {
+      WalkOut<MODE> o;
+      o.xhat = io.out_f32;
+      o.weight = io.in[rid] * r.dn;
+      if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, e, o, st);
     } else if constexpr (MODE == kModeCountPos) {
       WalkOut<MODE> o;
       if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
@@ -709,7 +769,10 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
       TCT_LAUNCH(kModeForward);
       break;
     case kModeBackAtomic:
-      TCT_LAUNCH(kModeBackAtomic);
+      if (lds_table)
+        TCT_LAUNCH(kModeBackAtomic);
+      else
+        TCT_LAUNCH(kModeBackDirect);
       break;
     case kModeCountPos:
       TCT_LAUNCH(kModeCountPos);
