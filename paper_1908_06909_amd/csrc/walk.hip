@@ -28,6 +28,8 @@
 // estimated in float32 as (q - p) . ((P - S) x (p - S)) with a certified
 // error bound; the rare uncertain cases go to a non-inlined float64 /
 // exact-expansion routine (exact.h).
+#include <type_traits>
+
 #include "common.h"
 #include "exact.h"
 #include "kernels.h"
@@ -58,8 +60,15 @@ struct Ray {
   float kR;    // 64 u^2 R, R bounding every coordinate met on this ray (walk filter)
 };
 
+// Per-lane walk statistics (events of one ray; reduced per wave at the end).
 struct LaneStats {
   int steps = 0, zero = 0, fp64 = 0, exact = 0, pert = 0, failed = 0, grazing = 0;
+  __device__ __forceinline__ void add_zero() { zero++; }
+  __device__ __forceinline__ void add_grazing() { grazing++; }
+  __device__ __forceinline__ void add_fp64() { fp64++; }
+  __device__ __forceinline__ void add_exact() { exact++; }
+  __device__ __forceinline__ void add_pert() { pert++; }
+  __device__ __forceinline__ void add_failed() { failed++; }
 };
 
 // The ray is carried with an exact direction d = d_hi + d_lo and an almost
@@ -98,6 +107,30 @@ __device__ __forceinline__ Ray cone_ray(const GeomView& g, float mesh_extent, in
   r.P = pixel_point(f, u, v);
   finish_ray(r, mesh_extent);
   return r;
+}
+
+// Where the walk's rare exact paths find the ray's endpoints and
+// tie-breaking axes.  Keeping them out of the step loop's live registers
+// matters: for pixel rays they are re-read from the angle's frame (uniform
+// across the block) and the pixel tables; listed rays carry them.
+struct PixelSrc {
+  const float* f;  // frame {S, D, U, V} of the ray's angle
+  float u, v;      // pixel abscissa and ordinate
+  __device__ __forceinline__ float3 S() const { return make_float3(f[0], f[1], f[2]); }
+  __device__ __forceinline__ float3 P() const { return pixel_point(f, u, v); }
+  __device__ __forceinline__ float3 U() const { return make_float3(f[6], f[7], f[8]); }
+  __device__ __forceinline__ float3 V() const { return make_float3(f[9], f[10], f[11]); }
+};
+struct RegSrc {
+  float3 s, p, uu, vv;
+  __device__ __forceinline__ float3 S() const { return s; }
+  __device__ __forceinline__ float3 P() const { return p; }
+  __device__ __forceinline__ float3 U() const { return uu; }
+  __device__ __forceinline__ float3 V() const { return vv; }
+};
+
+__device__ __forceinline__ PixelSrc pixel_src(const GeomView& g, int a, int i, int j) {
+  return PixelSrc{g.frame + 12 * a, g.ut[i], g.vt[j]};
 }
 
 // Ray parameter s = t - 1/2 where S + t (P - S) meets the plane through
@@ -150,9 +183,18 @@ constexpr float kWalkRel = 24.0f * 5.9604644775390625e-8f;
 __device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, LaneStats& st) {
   if (fast != 2) return fast;
   int res = slow_edge_sign(r.S, r.P, r.U, r.V, p, q);
-  st.fp64++;
-  if (res & (kFlagExact << 2)) st.exact++;
-  if (res & (kFlagPerturbed << 2)) st.pert++;
+  st.add_fp64();
+  if (res & (kFlagExact << 2)) st.add_exact();
+  if (res & (kFlagPerturbed << 2)) st.add_pert();
+  return (res & 3) - 1;
+}
+
+template <class Src>
+__device__ __forceinline__ int resolve_src(const Src& q, float3 a, float3 b, LaneStats& st) {
+  int res = slow_edge_sign(q.S(), q.P(), q.U(), q.V(), a, b);
+  st.add_fp64();
+  if (res & (kFlagExact << 2)) st.add_exact();
+  if (res & (kFlagPerturbed << 2)) st.add_pert();
   return (res & 3) - 1;
 }
 
@@ -279,8 +321,7 @@ __device__ __forceinline__ void lds_accumulate(int* keys, float* vals, int tet, 
 #pragma unroll 1
   for (int p = 0; p < kLdsProbes; ++p) {
     unsigned slot = (h + p) & (kLdsSlots - 1);
-    int k = keys[slot];
-    if (k == -1) k = atomicCAS(keys + slot, -1, tet);
+    int k = atomicCAS(keys + slot, -1, tet);
     if (k == -1 || k == tet) {
       // The table pointer arrives as a generic pointer; cast it back to the
       // LDS address space so the add is a native ds_add_f32 (through a
@@ -325,8 +366,8 @@ struct WalkState {
 };
 
 // Enter the mesh through boundary face `entry`.
-template <int MODE>
-__device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, int entry, WalkState& w,
+template <int MODE, class Src>
+__device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, const Src& q, int entry, WalkState& w,
                                            const WalkOut<MODE>& o) {
   const float4* bq = M.bfaces + 4 * (size_t)entry;
   float4 q0 = bq[0], q1 = bq[1], q2 = bq[2], q3 = bq[3];
@@ -344,7 +385,7 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, int 
   // crossing are evaluated from a vector of element size whose error is a
   // few ulps of itself, not of the source distance.  Only segment lengths
   // are accumulated, never differences of rounded parameters.
-  float s_in = (float)crossing_s_fp64(r.S, r.P, w.a0, w.a1, w.a2);
+  float s_in = (float)crossing_s_fp64(q.S(), q.P(), w.a0, w.a1, w.a2);
   w.s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
   w.xcur = 0.f;
   if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
@@ -354,11 +395,11 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, int 
 // One step: leave the current tetrahedron, apply the mode's action for its
 // segment, move to the neighbour.  Returns false once the ray has left the
 // mesh (or the walk failed).
-template <int MODE>
-__device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, WalkState& w, WalkOut<MODE>& o,
-                                          LaneStats& st) {
+template <int MODE, class Src>
+__device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const Src& q, WalkState& w,
+                                          WalkOut<MODE>& o, LaneStats& st) {
   if (w.steps > M.nt) {
-    st.failed++;
+    st.add_failed();
     return false;
   }
   w.steps++;
@@ -370,9 +411,9 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, WalkS
   int s0 = walk_sign(e0, wv, K);
   int s1 = walk_sign(e1, wv, K);
   int s2 = walk_sign(e2, wv, K);
-  if (s0 == 2) s0 = resolve(2, r, v, w.a0, st);
-  if (s1 == 2) s1 = resolve(2, r, v, w.a1, st);
-  if (s2 == 2) s2 = resolve(2, r, v, w.a2, st);
+  if (s0 == 2) s0 = resolve_src(q, v, w.a0, st);
+  if (s1 == 2) s1 = resolve_src(q, v, w.a1, st);
+  if (s2 == 2) s2 = resolve_src(q, v, w.a2, st);
   int k;
   float3 ei, ej;
   if (s0 < 0 && s1 > 0) {
@@ -388,7 +429,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, WalkS
     ei = e2;
     ej = e0;
   } else {
-    st.failed++;
+    st.add_failed();
     return false;
   }
   float3 n = f3cross(ei, ej);
@@ -397,17 +438,17 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, WalkS
   if (den * den >= kGrazingCos2 * r.dd * f3dot(n, n)) {
     dt = f3dot(D, n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
   } else {
-    st.grazing++;
+    st.add_grazing();
     const bool k0 = k == 0, k2 = k == 2;
     const float3 ai = make_float3(k2 ? w.a0.x : (k0 ? w.a1.x : w.a2.x), k2 ? w.a0.y : (k0 ? w.a1.y : w.a2.y),
                                   k2 ? w.a0.z : (k0 ? w.a1.z : w.a2.z));
     const float3 aj = make_float3(k2 ? w.a1.x : (k0 ? w.a2.x : w.a0.x), k2 ? w.a1.y : (k0 ? w.a2.y : w.a0.y),
                                   k2 ? w.a1.z : (k0 ? w.a2.z : w.a0.z));
-    dt = (float)(crossing_s_fp64(r.S, r.P, v, ai, aj) - (double)w.s_in);
+    dt = (float)(crossing_s_fp64(q.S(), q.P(), v, ai, aj) - (double)w.s_in);
   }
   dt = fminf(fmaxf(dt, 0.0f), fmaxf(0.5f - w.s_in, 0.0f));
   st.steps++;
-  if (dt == 0.f) st.zero++;
+  if (dt == 0.f) st.add_zero();
   // Next tetrahedron across the exit face (local face index loc[k]).
   const int tet = w.tet;
   unsigned f = (w.loc >> (2 * k)) & 3u;
@@ -461,12 +502,12 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, WalkS
 }
 
 // Walk one ray from boundary face `entry` to the boundary.
-template <int MODE>
-__device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, int entry, WalkOut<MODE>& o,
+template <int MODE, class Src>
+__device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, const Src& q, int entry, WalkOut<MODE>& o,
                                          LaneStats& st) {
   WalkState w;
-  walk_start<MODE>(M, r, entry, w, o);
-  while (walk_step<MODE>(M, r, w, o, st)) {
+  walk_start<MODE>(M, r, q, entry, w, o);
+  while (walk_step<MODE>(M, r, q, w, o, st)) {
   }
 }
 
@@ -529,7 +570,7 @@ struct BlockIO {
 //   kModeCountPos:   counts[rid - rid0] = positive-length visits
 //   kModeGatherFill: keys/vals at offsets[rid - rid0]
 // Every thread of the block must call it (the backprojection synchronises).
-template <int MODE>
+template <int MODE, bool kLeanSrc = false>
 __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G, const TileMap& tm, int64_t block,
                                            int a0, int na_chunk, const BlockIO& io, int* tkeys, float* tvals) {
   int a, i, j;
@@ -542,6 +583,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     }
     __syncthreads();
     Ray r;
+    PixelSrc q{};
     WalkOut<MODE> o;
     o.xhat = io.out_f32;
     o.lds_keys = tkeys;
@@ -551,10 +593,11 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     if (active) {
       int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
       r = cone_ray(G, M.extent, a, i, j);
+      q = pixel_src(G, a, i, j);
       int e = io.entry ? io.entry[rid] : find_entry(M, r, st);
       o.weight = io.in[rid] * r.dn;
       if (e >= 0 && o.weight != 0.f) {
-        walk_start<MODE>(M, r, e, w, o);
+        walk_start<MODE>(M, r, q, e, w, o);
         alive = true;
       }
     }
@@ -563,7 +606,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     // ever holds the tetrahedra of one window of the ray bundle.
     for (;;) {
 #pragma unroll 1
-      for (int k = 0; k < kLdsWindow && alive; ++k) alive = walk_step<MODE>(M, r, w, o, st);
+      for (int k = 0; k < kLdsWindow && alive; ++k) alive = walk_step<MODE>(M, r, q, w, o, st);
       const int any = __syncthreads_or(alive ? 1 : 0);
       for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
         const int key = tkeys[k];
@@ -580,22 +623,31 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
     int64_t rid0 = (int64_t)a0 * G.nv * G.nu;
     Ray r = cone_ray(G, M.extent, a, i, j);
+    // The single-problem walks have registers to spare, so their exact paths
+    // read the ray from registers; the batched ones (and the windowed
+    // backprojection) re-read it from the frame.
+    using Src = typename std::conditional<kLeanSrc, PixelSrc, RegSrc>::type;
+    Src q;
+    if constexpr (kLeanSrc)
+      q = pixel_src(G, a, i, j);
+    else
+      q = RegSrc{r.S, r.P, r.U, r.V};
     int e = (io.entry && MODE != kModeEntry) ? io.entry[rid] : find_entry(M, r, st);
     if constexpr (MODE == kModeEntry) {
       io.out_i32[rid] = e;
     } else if constexpr (MODE == kModeForward) {
       WalkOut<MODE> o;
       o.x = io.in;
-      if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+      if (e >= 0) walk_ray<MODE>(M, r, q, e, o, st);
       io.out_f32[rid] = (float)(o.acc * (double)r.dn);
     } else if constexpr (MODE == kModeBackDirect) {
       WalkOut<MODE> o;
       o.xhat = io.out_f32;
       o.weight = io.in[rid] * r.dn;
-      if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, e, o, st);
+      if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, q, e, o, st);
     } else if constexpr (MODE == kModeCountPos) {
       WalkOut<MODE> o;
-      if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+      if (e >= 0) walk_ray<MODE>(M, r, q, e, o, st);
       io.counts[rid - rid0] = o.count;
     } else if constexpr (MODE == kModeGatherFill) {
       WalkOut<MODE> o;
@@ -603,7 +655,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       o.out_tet = io.keys;
       o.out_len = io.vals;
       o.cursor = io.offsets[rid - rid0];
-      if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+      if (e >= 0) walk_ray<MODE>(M, r, q, e, o, st);
     }
   }
   flush_stats(M, st, active ? 1 : 0);
@@ -614,7 +666,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
 // ---------------------------------------------------------------- kernels
 
 template <int MODE>
-__global__ __launch_bounds__(256) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
+__global__ __launch_bounds__(256, MODE == kModeBackAtomic ? 4 : 1) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
                                                          BlockIO io) {
   if constexpr (MODE == kModeBackAtomic) {
     __shared__ int tkeys[kLdsSlots];
@@ -639,15 +691,22 @@ struct BatchDesc {
 };
 
 template <int MODE>
-__global__ __launch_bounds__(256) void batch_walk_kernel(const BatchDesc* D, int nprob, int64_t total,
-                                                         unsigned long long* counter, const float* const* ins,
-                                                         float* const* outs) {
+__global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __restrict__ D, int nprob, int64_t total,
+                                                         unsigned long long* counter,
+                                                         const float* const* __restrict__ ins,
+                                                         float* const* __restrict__ outs) {
   __shared__ long long s_item;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
     __syncthreads();
-    long long item = s_item;
+    // The item is the same for the whole block; saying so lets the
+    // descriptor below be read with scalar loads into scalar registers, as
+    // kernel arguments are in the single-problem kernel.
+    const long long raw = s_item;
+    const long long item = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(raw >> 32))
+                                        << 32) |
+                                       (unsigned)__builtin_amdgcn_readfirstlane((int)raw));
     if (item >= total) break;
     int lo = 0, hi = nprob - 1;
     while (lo < hi) {
@@ -657,7 +716,8 @@ __global__ __launch_bounds__(256) void batch_walk_kernel(const BatchDesc* D, int
       else
         hi = mid - 1;
     }
-    const BatchDesc& d = D[lo];
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const BatchDesc d = D[lo];
     BlockIO io{};
     io.entry = d.entry;
     io.in = ins[d.user];
@@ -666,9 +726,9 @@ __global__ __launch_bounds__(256) void batch_walk_kernel(const BatchDesc* D, int
     if constexpr (MODE == kModeBackAtomic) {
       __shared__ int tkeys[kLdsSlots];
       __shared__ float tvals[kLdsSlots];
-      walk_block<MODE>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
+      walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
     } else {
-      walk_block<MODE>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
+      walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
     }
   }
 }
@@ -704,7 +764,8 @@ __global__ __launch_bounds__(256) void list_walk_kernel(MeshView M, GeomView G, 
           v3[3] = {r.V.x, r.V.y, r.V.z};
     bool basis = det_diff_sign(p3, s3, u3, nullptr, v3, nullptr, nullptr) != 0;
     int e = basis ? find_entry(M, r, st) : -1;
-    if (!basis) st.failed++;
+    if (!basis) st.add_failed();
+    const RegSrc q{r.S, r.P, r.U, r.V};
     WalkOut<MODE> o;
     if constexpr (MODE == kModeTrace) {
       o.out_tet = tets;
@@ -712,7 +773,7 @@ __global__ __launch_bounds__(256) void list_walk_kernel(MeshView M, GeomView G, 
       o.perm = M.perm;
       o.cursor = offsets[k];
     }
-    if (e >= 0) walk_ray<MODE>(M, r, e, o, st);
+    if (e >= 0) walk_ray<MODE>(M, r, q, e, o, st);
     if constexpr (MODE == kModeCountAll) counts[k] = o.count;
   }
   flush_stats(M, st, active ? 1 : 0);
