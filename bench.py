@@ -24,6 +24,41 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# Measured HBM traffic of the walk kernels (rocprofv3 FETCH_SIZE / WRITE_SIZE
+# on this workload, scaled by a copy-kernel calibration), valid only for the
+# kernel sources it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_walk_kernels_kuhn64_jit_512x512x360.txt")
+KERNEL_SOURCES = ["walk.hip", "ray.h", "exact.h", "common.h", "kernels.h"]
+
+
+def kernel_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1908_06909_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic_bytes(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(("#", " ")))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256") != kernel_digest():
+        return None
+    try:
+        fetch = float(kv[kernel + ".fetch_kib"]) * float(kv["fetch_factor"])
+        write = float(kv[kernel + ".write_kib"]) * float(kv["write_factor"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) * 1024.0
 FWD_BYTES_PER_SEG = 24  # neighbour id + new vertex id + its xyz + x_i
 BWD_BYTES_PER_SEG = 28  # walk geometry (20) + read-modify-write of xhat_i (8)
 
@@ -253,9 +288,13 @@ def main():
                  "gather": "gather backprojection (walk fill + sort + segment sum)",
                  "shadow": "element-driven backprojection (shadow_backproject_kernel)"}[args.bp]
     if ms["forward"] >= ms["backproject"]:
-        dom, ach, bps = "forward walk (pixel_walk_kernel<1>)", fwd_gbs, FWD_BYTES_PER_SEG
+        dom, ach, bps, dom_ms, key = "forward walk (pixel_walk_kernel<1>)", fwd_gbs, FWD_BYTES_PER_SEG, ms["forward"], \
+            "pixel_walk_kernel<1>"
     else:
-        dom, ach, bps = bp_kernel, bwd_gbs, BWD_BYTES_PER_SEG
+        dom, ach, bps, dom_ms = bp_kernel, bwd_gbs, BWD_BYTES_PER_SEG, ms["backproject"]
+        key = {"atomic": "pixel_walk_kernel<2>", "atomic_direct": "pixel_walk_kernel<7>"}.get(args.bp, "")
+    traffic_bytes = measured_traffic_bytes(key) if (key and args.workload == 1 and not args.angles) else None
+    traffic = traffic_bytes / (dom_ms * 1e-3) / 1e9 if traffic_bytes else None
     out = {
         "metric": "tet-segments/s fwd+back at 1 GPU",
         "value": value,
@@ -285,7 +324,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_bytes_per_launch": traffic_bytes,
             "bytes_per_segment": bps,
         },
         "kernels_ms": ms,

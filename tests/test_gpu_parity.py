@@ -5,10 +5,11 @@ the mesh and |d_j| its full length |P - S|:
   * traversed-tetrahedron sequences, zero-length passages included: identical;
   * segment lengths: |L_gpu - L_ref| <= 1e-5 * max(chord_j, |d_j| / 64).
     The floor: the kernels keep ray parameters as float32 numbers in
-    [-1/2, 1/2], whose rounding moves a crossing by up to ~2^-25 |d_j|, up to
-    8x more for crossings just above the float64 grazing threshold; 1e-5/64
-    = 2^-22.6 covers a few such errors.  It matters only for rays that clip
-    the hull with a chord shorter than |d_j| / 64;
+    [-1/2, 1/2], whose rounding moves a crossing by up to ~2^-25 |d_j|, and a
+    float32 crossing of a face at angle phi to the ray moves by ~5 u h / cos
+    phi for an element of size h (float64 below cos phi = 1/64); 1e-5/64 =
+    2^-22.6 covers a few such errors.  It matters only for rays that clip the
+    hull with a chord shorter than |d_j| / 64;
   * projections: |b_gpu - b_ref| <= 1e-5 * sum_i a_ij |x_i|
     + 1e-5 (|d_j| / 64) TV_j(x), TV_j = sum over the ray's crossings of the
     jump of x (length errors telescope); misses exactly 0;
