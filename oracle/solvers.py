@@ -3,8 +3,9 @@
 TEST INFRASTRUCTURE ONLY.  The paper's operator A (Section II-A, Eq. 1:
 a_ij = length of ray j inside tetrahedron i) is assembled explicitly from the
 oracle's traced walks as a scipy sparse matrix, and the textbook algorithms
-the paper names as consumers of A and A^T (CGLS, SART-family SIRT) are
-written out plainly in float64.
+the paper names as consumers of A and A^T (CGLS, SART-family SIRT, and the
+ordered-subset SART of its reconstructions, Section III-A) are written out
+plainly in float64.
 """
 
 from __future__ import annotations
@@ -80,4 +81,35 @@ def sirt(A, b, iters: int, lam: float = 1.0, x0=None):
         r = b - A @ x
         rr.append(float(r @ r))
         x = x + lam * Cw * (A.T @ (R * r))
+    return x, np.array(rr)
+
+
+def os_sart(A, b, iters: int, subsets, lam: float = 1.0, x0=None):
+    """Ordered-subset SART (the reconstructions of Section III-A: blocks of
+    projections).  One iteration visits the row subsets in the given order;
+    for subset k with rows A_k:
+
+        x += lam * C_k A_k^T R_k (b_k - A_k x),
+        R_k = diag(1 / row sums of A_k),  C_k = diag(1 / column sums of A_k),
+
+    zero where a sum is zero.  Returns (x, rr) with rr[k] = ||b - A x_k||^2
+    before iteration k.
+    """
+    A = sp.csr_matrix(A)
+    parts = []
+    for rows in subsets:
+        rows = np.asarray(rows, np.int64)
+        Ak = A[rows]
+        row = np.asarray(Ak.sum(axis=1)).ravel()
+        col = np.asarray(Ak.sum(axis=0)).ravel()
+        R = np.where(row > 0, 1.0 / np.where(row > 0, row, 1.0), 0.0)
+        Cw = np.where(col > 0, 1.0 / np.where(col > 0, col, 1.0), 0.0)
+        parts.append((Ak, b[rows], R, Cw))
+    x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
+    rr = []
+    for _ in range(iters):
+        r = b - A @ x
+        rr.append(float(r @ r))
+        for Ak, bk, R, Cw in parts:
+            x = x + lam * Cw * (Ak.T @ (R * (bk - Ak @ x)))
     return x, np.array(rr)

@@ -1,7 +1,8 @@
 """Pins of the float64 reference solvers: the explicit matrix reproduces the
 oracle's walks, the gradient matches central differences (exact for a
 quadratic up to rounding), CGLS is monotone and reaches the least-squares
-solution of the dense normal equations, SIRT decreases its weighted residual."""
+solution of the dense normal equations, SIRT decreases its weighted residual,
+OS-SART reproduces a hand-worked iteration and converges on a consistent system."""
 
 import numpy as np
 import pytest
@@ -76,3 +77,36 @@ def test_sirt_decreases_weighted_residual(small):
         assert cur <= prev * (1 + 1e-12)
         prev = cur
         x = x + C * (A.T @ (R * r))
+
+
+def test_os_sart_hand_worked_iteration():
+    # A = [[1, 2], [3, 1]], b = (5, 5), subsets {row 0}, {row 1}, x0 = 0, lam = 1.
+    # Row 0: R = 1/3, C = (1/1, 1/2): x = (1, 1/2) * (1, 2) * 5/3 = (5/3, 5/3).
+    # Row 1: A_1 x = 20/3, residual -5/3, R = 1/4, C = (1/3, 1/1):
+    #   x += (1/3, 1) * (3, 1) * (-5/12) = (-5/12, -5/12)  ->  x = (5/4, 5/4).
+    import scipy.sparse as sp
+
+    A = sp.csr_matrix(np.array([[1.0, 2.0], [3.0, 1.0]]))
+    b = np.array([5.0, 5.0])
+    x, rr = solvers.os_sart(A, b, 1, [[0], [1]])
+    assert np.allclose(x, [1.25, 1.25], rtol=0, atol=1e-15)
+    assert rr[0] == 50.0
+    # second iteration, row 0: A_0 x = 15/4, r = 5/4, R = 1/3 -> x += (1, 1/2)(1, 2) 5/12 = 5/12 each
+    x2, _ = solvers.os_sart(A, b, 2, [[0], [1]])
+    # then row 1: A_1 x = 3 * 5/3 + 5/3 = 20/3 again -> the same correction -5/12 each
+    assert np.allclose(x2, [1.25, 1.25], rtol=0, atol=1e-15)
+
+
+def test_os_sart_converges_on_consistent_system(small):
+    w, o, A = small
+    rng = np.random.default_rng(4)
+    xt = rng.uniform(0, 1, o.nt)
+    b = A @ xt
+    per_angle = w.cone.nu * w.cone.nv
+    subsets = [np.arange(a * per_angle, (a + 2) * per_angle) for a in range(0, len(w.angles), 2)]
+    x, rr = solvers.os_sart(A, b, 200, subsets)
+    assert rr[-1] <= 1e-6 * rr[0]
+    # with one subset holding every row it is SIRT
+    xs, rrs = solvers.sirt(A, b, 5)
+    x1, rr1 = solvers.os_sart(A, b, 5, [np.arange(o.nrays)])
+    assert np.allclose(x1, xs, rtol=1e-12, atol=1e-14) and np.allclose(rr1, rrs, rtol=1e-12)
