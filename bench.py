@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--gather", action="store_true")
+    ap.add_argument("--os-sart", type=int, default=0, metavar="BLOCK",
+                    help="time OS-SART sweeps with blocks of BLOCK consecutive angles instead")
     ap.add_argument("--bp", default="atomic", choices=["atomic", "shadow", "atomic_direct", "gather"],
                     help="backprojection of the timed step")
     ap.add_argument("--json-extra", default=None)
@@ -120,6 +122,40 @@ def cpu_baseline(w, budget_s):
         "sample": f"every {k}-th ray ({len(ids)} rays, {segs} segments fwd+back) of the same workload; "
                   f"forward {t1 - t0:.1f}s, backprojection {t2 - t1:.1f}s; mesh build {build_s:.1f}s untimed",
     }
+
+
+def os_sart_bench(args):
+    """OS-SART sweeps (blocks of consecutive angles, range launches) on the benchmark workload."""
+    import torch
+
+    import paper_1908_06909_amd as tct
+    import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.config(args.workload)
+    mesh = tct.TetMesh(w.verts, w.tets, device=dev)
+    geom = tct.ConeGeometry(w.cone, w.angles, device=dev)
+    P = tct.Projector(mesh, geom)
+    xt = mesh.to_internal(torch.as_tensor(w.x, device=dev))
+    b = P.forward(xt).reshape(-1).clone()
+    solver = tct.OSSART(P, b, block=args.os_sart, bp_mode=args.bp)
+    r0 = float(solver.residual().item())
+    solver.run(args.warmup, track=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    solver.run(args.steps, track=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    r = float(solver.residual().item())
+    err = float((solver.x - xt).double().norm() / xt.double().norm())
+    out = {
+        "metric": "OS-SART sweeps/s", "value": args.steps / el, "unit": "sweeps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_sweep": el * 1e3 / args.steps,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "block": args.os_sart, "blocks": len(solver.blocks), "bp": args.bp},
+        "residual_ratio_after": r / r0, "relative_error_after": err, "sweeps_done": args.steps + args.warmup,
+    }
+    print(json.dumps(out))
 
 
 def batch_cgls_bench(args):
@@ -225,6 +261,9 @@ def main():
 
     if args.batch_cgls:
         batch_cgls_bench(args)
+        return
+    if args.os_sart:
+        os_sart_bench(args)
         return
 
     dev = torch.device("cuda:0")

@@ -10,9 +10,9 @@ from .projector import ConeGeometry, Projector, TetMesh, trace_rays
 
 __all__ = ["TetMesh", "ConeGeometry", "Projector", "trace_rays"]
 
-from .solvers import CGLS, TetProject, cgls, project, sirt  # noqa: E402
+from .solvers import CGLS, OSSART, TetProject, cgls, os_sart, project, sirt  # noqa: E402
 
-__all__ += ["TetProject", "project", "CGLS", "cgls", "sirt"]
+__all__ += ["TetProject", "project", "CGLS", "cgls", "sirt", "OSSART", "os_sart"]
 
 from .batch import BatchCGLS, BatchProjector, PlainCGLS, SetOps, VecSet  # noqa: E402
 from . import autotune  # noqa: E402

@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_GATHER, TCT_BP_SHADOW, call, lib, tct_cone, tct_stats
+from ._lib import (TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_GATHER, TCT_BP_SHADOW, call, lib, tct_cone,
+                   tct_range, tct_stats)
 
 
 def _stream(device) -> int:
@@ -190,6 +191,34 @@ class Projector:
              _ptr(y, torch.float32, self.mesh.device_index, self.geom.nrays, "proj"),
              _ptr(out, torch.float32, self.mesh.device_index, self.nt, "xhat"), m, 1 if accumulate else 0,
              self._entry_ptr(use_cache), _stream(self.device))
+        return out
+
+    _BP_MODES = {"atomic": TCT_BP_ATOMIC, "atomic_direct": TCT_BP_ATOMIC_DIRECT, "gather": TCT_BP_GATHER,
+                 "shadow": TCT_BP_SHADOW}
+
+    def forward_range(self, x: torch.Tensor, a0: int, na: int, out: torch.Tensor, tile_u: int = 8,
+                      use_cache: bool = True) -> torch.Tensor:
+        """A x for the angles [a0, a0 + na) only, into their slab of the full
+        [na_total, nv, nu] array ``out`` (other angles untouched)."""
+        call("tct_forward_range", self.mesh.handle, self.geom.handle,
+             _ptr(x, torch.float32, self.mesh.device_index, self.nt, "x"),
+             _ptr(out, torch.float32, self.mesh.device_index, self.geom.nrays, "proj"),
+             self._entry_ptr(use_cache), C.byref(tct_range(int(a0), int(na), int(tile_u))), _stream(self.device))
+        return out
+
+    def backproject_range(self, y: torch.Tensor, a0: int, na: int, mode: str = "atomic",
+                          out: Optional[torch.Tensor] = None, accumulate: bool = False, tile_u: int = 8,
+                          use_cache: bool = True) -> torch.Tensor:
+        """A^T y restricted to the rays of the angles [a0, a0 + na) (y keeps
+        the full [na_total, nv, nu] layout)."""
+        if out is None:
+            out = torch.empty(self.nt, dtype=torch.float32, device=self.device)
+            accumulate = False
+        call("tct_backproject_range", self.mesh.handle, self.geom.handle,
+             _ptr(y, torch.float32, self.mesh.device_index, self.geom.nrays, "proj"),
+             _ptr(out, torch.float32, self.mesh.device_index, self.nt, "xhat"), self._BP_MODES[mode],
+             1 if accumulate else 0, self._entry_ptr(use_cache), C.byref(tct_range(int(a0), int(na), int(tile_u))),
+             _stream(self.device))
         return out
 
     def compute_entry(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -6,6 +6,9 @@
 * float32 directional central differences of the same loss on the GPU;
 * CGLS residual history vs float64 CGLS on the oracle's matrix;
 * SIRT residual history vs float64 SIRT;
+* OS-SART (blocks of consecutive angles through range launches) residual
+  history and iterate vs float64 OS-SART on the oracle's matrix, with the
+  scatter and the element-driven backprojection;
 * 50 CGLS iterations on the 64^3 jittered mesh / 512^2 x 360 geometry
   reconstructing the sphere phantom from its own projections: residual and
   error norms non-increasing.
@@ -124,6 +127,22 @@ def test_sirt_history_matches_oracle():
     _, rr_ref = osolv.sirt(S.A, S.b, iters)
     rel = np.abs(rr - rr_ref) / rr_ref
     assert np.all(rel <= 1e-4), rel
+
+
+@pytest.mark.parametrize("bp_mode", ["atomic", "shadow"])
+def test_os_sart_history_matches_oracle(bp_mode):
+    S = setup()
+    iters, block = 8, 5  # 16 angles: blocks of 5, 5, 5, 1
+    per_angle = S.w.cone.nu * S.w.cone.nv
+    na = len(S.w.angles)
+    subsets = [np.arange(a * per_angle, min(a + block, na) * per_angle) for a in range(0, na, block)]
+    x, rr = S.tct.os_sart(S.P, S.b_t, iters, block=block, bp_mode=bp_mode)
+    x_ref, rr_ref = osolv.os_sart(S.A, S.b, iters, subsets)
+    rel = np.abs(rr - rr_ref) / rr_ref
+    assert np.all(rel <= 1e-4), rel
+    xu = S.user(x)
+    assert np.linalg.norm(xu - x_ref) <= 1e-4 * np.linalg.norm(x_ref)
+    assert rr[-1] < 0.05 * rr[0]
 
 
 def test_cgls_50_iterations_on_jittered_64():
