@@ -667,6 +667,160 @@ Cone cone_from(const double* c) {
 // ---------------------------------------------------------------------------
 // C interface used by the Python test harness.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// The paper's own propagation (Algorithms 1 and 2), for the comparison of
+// single and double precision (Section III-C).  Written from the algorithms:
+//   Algorithm 1: Moller-Trumbore on triangle (P1, P2, P3) with safety eps:
+//     d = R2 - R1, E1 = P2 - P1, E2 = P3 - P1, q = d x E2, a = E1 . q;
+//     reject |a| < 1e-8; f = 1 / a; s = R1 - P1; u = f (s . q), reject u < -eps;
+//     r = s x E1; v = f (d . r), reject v < -eps or u + v > 1 + eps; t = f (E2 . r).
+//   Algorithm 2: per tetrahedron test the four faces with eps = 1e-9, x10
+//     until two faces are hit; add l (t2 - t1) x; step across the t2 face.
+// Readings (the same ones the library documents): v uses the dot product d . r;
+// past eps = 1 the ray halts; t1 = smallest parameter hit, the exit is the
+// face with the largest parameter other than the face the ray came in by,
+// lowest index on ties; 16384 steps at most (else "looping"); the ray enters
+// through the boundary face found exactly.  Local vertex order: ascending
+// node ids, the last two swapped if negatively oriented; face k opposite
+// vertex k, its other vertices in increasing local order.  Arithmetic in a
+// fixed order without contraction (the file is built with -ffp-contract=off).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PV {
+  T x, y, z;
+};
+template <typename T>
+PV<T> psub(const PV<T>& a, const PV<T>& b) {
+  return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+template <typename T>
+T pdot(const PV<T>& a, const PV<T>& b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename T>
+PV<T> pcross(const PV<T>& a, const PV<T>& b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+template <typename T>
+bool moller_trumbore(const PV<T>& R1, const PV<T>& d, const PV<T>& P1, const PV<T>& P2, const PV<T>& P3, T eps,
+                     T* t) {
+  PV<T> E1 = psub(P2, P1), E2 = psub(P3, P1);
+  PV<T> q = pcross(d, E2);
+  T a = pdot(E1, q);
+  const T tiny = (T)1e-8;
+  if (a > -tiny && a < tiny) return false;
+  T f = (T)1 / a;
+  PV<T> s = psub(R1, P1);
+  T u = f * pdot(s, q);
+  if (u < (T)0 - eps) return false;
+  PV<T> r = pcross(s, E1);
+  T v = f * pdot(d, r);
+  if (v < (T)0 - eps || u + v > (T)1 + eps) return false;
+  *t = f * pdot(E2, r);
+  return true;
+}
+
+struct PaperCounts {
+  long long rays = 0, steps = 0, escalations = 0, halted = 0, looped = 0;
+};
+
+// Canonical local order of tetrahedron t and the neighbour across each face.
+void canonical_tet(const Mesh& m, int t, int v[4], int nb[4]) {
+  int ids[4] = {m.T[t][0], m.T[t][1], m.T[t][2], m.T[t][3]};
+  std::sort(ids, ids + 4);
+  if (orient3d(m.p(ids[0]), m.p(ids[1]), m.p(ids[2]), m.p(ids[3])) < 0) std::swap(ids[2], ids[3]);
+  for (int k = 0; k < 4; ++k) {
+    v[k] = ids[k];
+    nb[k] = -1;
+    for (int j = 0; j < 4; ++j)
+      if (m.T[t][j] == ids[k]) nb[k] = m.N[t][j];
+  }
+}
+
+template <typename T>
+double paper_ray(const Mesh& m, const Ray& r, const float* x, PaperCounts* pc) {
+  // Exact entry (brute force over the boundary, as in walk()).
+  int cur = -1, opp = -1;
+  SignStats sg;
+  for (const auto& bf : m.bfaces)
+    if (face_cross(m, r, m.F[bf[0]][bf[1]], &sg) == -1) {
+      cur = bf[0];
+      opp = m.T[bf[0]][bf[1]];
+      break;
+    }
+  if (cur < 0) return 0.0;
+  pc->rays++;
+  PV<T> R1 = {(T)r.S[0], (T)r.S[1], (T)r.S[2]}, R2 = {(T)r.P[0], (T)r.P[1], (T)r.P[2]};
+  PV<T> d = psub(R2, R1);
+  T l = std::sqrt(pdot(d, d));
+  T sum = 0;
+  int v[4], nb[4];
+  canonical_tet(m, cur, v, nb);
+  int prev = 0;
+  for (int k = 0; k < 4; ++k)
+    if (v[k] == opp) prev = k;
+  static const int kFace[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+  for (int step = 0;; ++step) {
+    if (step >= 16384) {
+      pc->looped++;
+      break;
+    }
+    pc->steps++;
+    PV<T> P[4];
+    for (int k = 0; k < 4; ++k) P[k] = {(T)m.p(v[k])[0], (T)m.p(v[k])[1], (T)m.p(v[k])[2]};
+    T eps = (T)1e-9, t1 = 0, t2 = 0;
+    int exit = -1;
+    bool halted = false;
+    for (;;) {
+      T th[4];
+      bool hit[4];
+      int nhit = 0;
+      for (int k = 0; k < 4; ++k) {
+        hit[k] = moller_trumbore(R1, d, P[kFace[k][0]], P[kFace[k][1]], P[kFace[k][2]], eps, &th[k]);
+        nhit += hit[k] ? 1 : 0;
+      }
+      if (nhit >= 2) {
+        bool first = true;
+        for (int k = 0; k < 4; ++k)
+          if (hit[k] && (first || th[k] < t1)) {
+            t1 = th[k];
+            first = false;
+          }
+        for (int k = 0; k < 4; ++k)
+          if (hit[k] && k != prev && (exit < 0 || th[k] > t2)) {
+            t2 = th[k];
+            exit = k;
+          }
+        if (exit >= 0) break;
+      }
+      eps = eps * (T)10;
+      pc->escalations++;
+      if (eps > (T)1) {
+        halted = true;
+        break;
+      }
+    }
+    if (halted) {
+      pc->halted++;
+      break;
+    }
+    sum = sum + l * (t2 - t1) * (T)x[cur];
+    int next = nb[exit];
+    if (next < 0) break;
+    int nv[4], nnb[4];
+    canonical_tet(m, next, nv, nnb);
+    int back = 0;
+    for (int k = 0; k < 4; ++k)
+      if (nnb[k] == cur) back = k;
+    cur = next;
+    std::memcpy(v, nv, sizeof v);
+    std::memcpy(nb, nnb, sizeof nb);
+    prev = back;
+  }
+  return (double)sum;
+}
+
 extern "C" {
 
 const char* orc_last_error(void) { return g_err.c_str(); }
@@ -885,6 +1039,49 @@ int orc_trace_rays(void* h, const float* S, const float* P, const float* U, cons
     std::memcpy(rays[i].V, V + 3 * i, 12);
   }
   return trace_common(*(const Mesh*)h, rays, offsets, tets, lens, cap);
+}
+
+
+// The paper's propagation (see paper_ray) for the listed rays (all when ids
+// is NULL) in float32 (precision 32) or float64 (64).  out[i] is the ray's
+// sum rounded to float32 and widened; counts = {rays, steps, escalations,
+// halted, looped}.
+int orc_forward_paper(void* h, const double* cone, const double* angles, int na, const float* x, const long long* ids,
+                      long long n, int precision, double* out, long long* counts, int nthreads) {
+  const Mesh& m = *(const Mesh*)h;
+  if (precision != 32 && precision != 64) {
+    g_err = "precision must be 32 or 64";
+    return E_ARG;
+  }
+  Frame f = make_frame(cone_from(cone), angles, na);
+  long long total = (long long)na * f.nu * f.nv;
+  if (!ids) n = total;
+  int nth = nthreads_of(nthreads);
+  std::vector<PaperCounts> pc(nth);
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nth)
+  for (long long i = 0; i < n; ++i) {
+    long long rid = ids ? ids[i] : i;
+    Ray r = make_ray(f, rid);
+    PaperCounts& c = pc[thread_id()];
+    double v = precision == 64 ? paper_ray<double>(m, r, x, &c) : paper_ray<float>(m, r, x, &c);
+    out[i] = (double)(float)v;
+  }
+  PaperCounts t;
+  for (auto& c : pc) {
+    t.rays += c.rays;
+    t.steps += c.steps;
+    t.escalations += c.escalations;
+    t.halted += c.halted;
+    t.looped += c.looped;
+  }
+  if (counts) {
+    counts[0] = t.rays;
+    counts[1] = t.steps;
+    counts[2] = t.escalations;
+    counts[3] = t.halted;
+    counts[4] = t.looped;
+  }
+  return OK;
 }
 
 }  // extern "C"

@@ -62,6 +62,8 @@ def lib():
     L.orc_rays.argtypes = [_f64p, _f64p, C.c_int, _i64p, C.c_longlong, _f32p, _f32p, _f32p, _f32p]
     L.orc_forward.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f32p, C.c_void_p, C.c_longlong, _f64p,
                               C.c_void_p, C.c_int]
+    L.orc_forward_paper.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f32p, C.c_void_p, C.c_longlong, C.c_int,
+                                    _f64p, _i64p, C.c_int]
     L.orc_backproject.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f32p, C.c_void_p, C.c_longlong, _f64p,
                                   C.c_int]
     L.orc_trace.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _i64p, C.c_longlong, _i64p, _i32p, _f64p,
@@ -219,6 +221,20 @@ class Oracle:
                                self.nthreads)
         self._check(st)
         return (out, cnt) if return_counts else out
+
+    def forward_paper(self, x, precision=64, ids=None):
+        """The paper's Moller-Trumbore / eps-escalation propagation (Algorithms
+        1-2) in float32 or float64 for the listed rays; returns (b rounded to
+        float32, counts {rays, steps, escalations, halted, looped})."""
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        ids_a, n = self._ids(ids)
+        out = np.zeros(n, np.float64)
+        cnt = np.zeros(5, np.int64)
+        st = lib().orc_forward_paper(self.mesh._h, self._cone, self.angles, self.na, x,
+                                     None if ids_a is None else ids_a.ctypes.data, n, int(precision), out, cnt,
+                                     self.nthreads)
+        self._check(st)
+        return out, dict(zip(("rays", "steps", "escalations", "halted", "looped"), (int(c) for c in cnt)))
 
     def backproject(self, y, ids=None):
         """xhat_i = sum_j a_ij y_j over the listed rays (y given per listed ray), float64."""
