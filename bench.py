@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--gather", action="store_true")
     ap.add_argument("--os-sart", type=int, default=0, metavar="BLOCK",
                     help="time OS-SART sweeps with blocks of BLOCK consecutive angles instead")
+    ap.add_argument("--paper-mode", action="store_true",
+                    help="compare the paper's Moller-Trumbore propagation (float32, float64) with the exact walk")
     ap.add_argument("--bp", default="atomic", choices=["atomic", "shadow", "atomic_direct", "gather"],
                     help="backprojection of the timed step")
     ap.add_argument("--json-extra", default=None)
@@ -122,6 +124,47 @@ def cpu_baseline(w, budget_s):
         "sample": f"every {k}-th ray ({len(ids)} rays, {segs} segments fwd+back) of the same workload; "
                   f"forward {t1 - t0:.1f}s, backprojection {t2 - t1:.1f}s; mesh build {build_s:.1f}s untimed",
     }
+
+
+def paper_mode_bench(args):
+    """The paper's propagation in float32 and float64 against the exact walk
+    (the single versus double precision experiment, on a synthetic stand-in)."""
+    import torch
+
+    import paper_1908_06909_amd as tct
+    import synth
+
+    dev = torch.device("cuda:0")
+    w = synth.config(args.workload)
+    mesh = tct.TetMesh(w.verts, w.tets, device=dev)
+    geom = tct.ConeGeometry(w.cone, w.angles, device=dev)
+    P = tct.Projector(mesh, geom)
+    x = mesh.to_internal(torch.as_tensor(w.x, device=dev))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t) * 1e3
+
+    exact, t_exact = timed(lambda: P.forward(x))
+    mesh.stats(reset=True)
+    exact = exact.reshape(-1).double()
+    hit = int((exact != 0).sum())
+    out = {"metric": "paper-faithful propagation vs exact walk", "config": {"workload": w.name, "rays": geom.nrays,
+           "rays_hitting": hit}, "exact_ms": t_exact, "data": "synthetic"}
+    for prec in (32, 64):
+        (b, st), ms = timed(lambda: P.forward_paper(x, prec))
+        b = b.reshape(-1).double()
+        err = (b - exact).abs()
+        tol = 1e-5 * torch.clamp(exact.abs(), min=1e-3)
+        out[f"float{prec}"] = dict(st, ms=ms, rays_off_by_more_than_1e_5=int((err > tol).sum()),
+                                   rays_off_by_more_than_1e_2=int((err > 1e-2 * torch.clamp(exact.abs(), min=1e-3))
+                                                                  .sum()),
+                                   escalations_per_million_rays=st["escalations"] / max(1, st["rays"]) * 1e6,
+                                   max_abs_error=float(err.max()))
+    print(json.dumps(out))
 
 
 def os_sart_bench(args):
@@ -264,6 +307,9 @@ def main():
         return
     if args.os_sart:
         os_sart_bench(args)
+        return
+    if args.paper_mode:
+        paper_mode_bench(args)
         return
 
     dev = torch.device("cuda:0")

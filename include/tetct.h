@@ -206,6 +206,28 @@ tct_status tct_forward_range(const tct_mesh* m, const tct_geom* g, const float* 
 tct_status tct_backproject_range(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
                                  int accumulate, const int32_t* entry, const tct_range* r, tct_stream s);
 
+/* Paper-faithful forward projection (Algorithms 1 and 2, Section II): the
+ * Moller-Trumbore test with the safety parameter eps (from 1e-9, x10 per
+ * failure to find two faces, halted past 1) on the four faces of each
+ * tetrahedron, stepping across the face with the larger parameter, in
+ * float32 (precision 32) or float64 (64) arithmetic.  For comparison with the
+ * exact walk (the paper's single versus double precision experiment, Section
+ * III-C); rays that halt or exceed 16384 steps keep their partial sums.
+ *   x          device float [nt], internal order
+ *   proj       device float [na][nv][nu], overwritten
+ *   entry      device int32 [nrays] from tct_entry (required)
+ *   stats      host, filled when not NULL (then the stream is synchronised) */
+typedef struct {
+  int64_t rays;         /* rays that entered the mesh */
+  int64_t steps;        /* tetrahedra visited */
+  int64_t escalations;  /* eps increases */
+  int64_t halted;       /* rays stopped because eps passed 1 */
+  int64_t looped;       /* rays stopped at the step cap */
+} tct_paper_stats;
+
+tct_status tct_forward_paper(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
+                             int precision, tct_paper_stats* stats, tct_stream s);
+
 /* Visited tetrahedra of selected rays, zero-length passages included, in CSR form.
  *   ray_ids  device int64 [nrays]
  *   offsets  device int64 [nrays + 1]   written: ray k owns [offsets[k], offsets[k+1])

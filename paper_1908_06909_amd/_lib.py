@@ -59,6 +59,13 @@ class tct_stats(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
+class tct_paper_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("rays", "steps", "escalations", "halted", "looped")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
 # name -> (restype, argtypes); pointers are passed as integers (c_void_p).
 _P = C.c_void_p
 _SIGS = {
@@ -87,6 +94,7 @@ _SIGS = {
     "tct_recip": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P]),
     "tct_copy_f64": (C.c_int, [_P, _P, C.c_int32, _P]),
     "tct_forward_range": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "tct_forward_paper": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.POINTER(tct_paper_stats), _P]),
     "tct_backproject_range": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, _P, _P, _P]),
     "tct_vecset_create": (C.c_int, [C.c_int32, _P, _P, C.c_int, C.POINTER(_P)]),
     "tct_vecset_destroy": (None, [_P]),

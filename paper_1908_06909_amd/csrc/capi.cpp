@@ -311,6 +311,22 @@ tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* pr
                             (hipStream_t)s);
 }
 
+tct_status tct_forward_paper(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
+                             int precision, tct_paper_stats* stats, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!x || !proj || !entry) {
+    set_error("tct_forward_paper: null input, output or entry cache");
+    return TCT_E_ARG;
+  }
+  if (precision != 32 && precision != 64) {
+    set_error("tct_forward_paper: precision must be 32 or 64");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return forward_paper(m, g, x, proj, entry, precision, stats, (hipStream_t)s);
+}
+
 namespace {
 tct_status trace_common(const tct_mesh* m, const tct_geom* g, const int64_t* ids, const float* S, const float* P,
                         const float* U, const float* V, int32_t n, int64_t* offsets, int32_t* tets, float* lens,

@@ -52,6 +52,7 @@ struct MeshView {
   // (v0.xyz v1.xyz v2.xyz v3.xyz), ordered so that
   // det[v1 - v0, v2 - v0, v3 - v0] > 0.
   const float4* tetxyz;
+  const int32_t* tetnbr;  // [nt][4] neighbour across the face opposite tetxyz vertex k, -1 = boundary
 };
 
 // Cone-beam frames: frame[12 a + 0..11] = S, D, U, V of angle a.
@@ -98,6 +99,7 @@ struct tct_mesh {
   float4* d_faces = nullptr;
   float4* d_bfaces = nullptr;
   float4* d_tetxyz = nullptr;
+  int32_t* d_tetnbr = nullptr;
   tct::BvhNode* d_bvh = nullptr;
   int32_t* d_perm = nullptr;
   int32_t* d_inv_perm = nullptr;
@@ -114,6 +116,7 @@ struct tct_mesh {
     v.nb = nb;
     v.counters = d_counters;
     v.tetxyz = d_tetxyz;
+    v.tetnbr = d_tetnbr;
     v.extent = 0.f;
     for (int k = 0; k < 3; ++k) v.extent = std::max(v.extent, std::max(std::fabs(lo[k]), std::fabs(hi[k])));
     return v;

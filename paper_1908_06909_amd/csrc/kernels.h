@@ -1,4 +1,4 @@
-// Kernel launchers (walk.hip, gather.hip, shadow.hip) used by the C interface.
+// Kernel launchers (walk.hip, gather.hip, shadow.hip, paper_mode.hip) used by the C interface.
 #pragma once
 
 #include "common.h"
@@ -36,6 +36,9 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
 
 tct_status backproject_shadow(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
                               int a_begin, int a_count, hipStream_t s);
+
+tct_status forward_paper(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
+                         int precision, tct_paper_stats* stats, hipStream_t s);
 
 tct_status batch_build(const tct_mesh* const* meshes, const tct_geom* const* geoms, int32_t n, const int32_t* tile_u,
                        int32_t* const* entries, tct_batch** out);

@@ -372,11 +372,21 @@ tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32
   }
   // Vertex coordinates per tetrahedron for the element-driven kernels, in
   // positive orientation (v2 and v3 swapped when the sorted order is negative).
+  // tetnbr[4 i + k]: internal neighbour across the face opposite tetxyz
+  // vertex k (-1 on the boundary), for the element-table walk of the
+  // paper-faithful mode.
   std::vector<float4> tetxyz(3 * (size_t)nt);
+  std::vector<int32_t> tetnbr(4 * (size_t)nt);
   for (int i = 0; i < nt; ++i) {
     const int32_t* q = &Ts[4 * (size_t)m->perm[i]];
     int idx[4] = {q[0], q[1], q[2], q[3]};
-    if (orient3d_sign(P(idx[0]), P(idx[1]), P(idx[2]), P(idx[3])) < 0) std::swap(idx[2], idx[3]);
+    const bool flip = orient3d_sign(P(idx[0]), P(idx[1]), P(idx[2]), P(idx[3])) < 0;
+    if (flip) std::swap(idx[2], idx[3]);
+    for (int k = 0; k < 4; ++k) {
+      const int f = flip && k >= 2 ? 5 - k : k;  // sorted-order face of local face k
+      const int nb_user = nbr[4 * (size_t)m->perm[i] + f];
+      tetnbr[4 * (size_t)i + k] = nb_user < 0 ? -1 : m->inv_perm[nb_user];
+    }
     float c[12];
     for (int k = 0; k < 4; ++k)
       for (int x = 0; x < 3; ++x) c[3 * k + x] = P(idx[k])[x];
@@ -396,6 +406,7 @@ tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32
   if ((st = upload(faces, &m->d_faces, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(bfaces, &m->d_bfaces, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(tetxyz, &m->d_tetxyz, &m->device_bytes)) != TCT_OK) return fail(st);
+  if ((st = upload(tetnbr, &m->d_tetnbr, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(nodes, &m->d_bvh, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(m->perm, &m->d_perm, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(m->inv_perm, &m->d_inv_perm, &m->device_bytes)) != TCT_OK) return fail(st);
@@ -410,6 +421,7 @@ void mesh_free_device(tct_mesh* m) {
   if (m->d_faces) (void)hipFree(m->d_faces);
   if (m->d_bfaces) (void)hipFree(m->d_bfaces);
   if (m->d_tetxyz) (void)hipFree(m->d_tetxyz);
+  if (m->d_tetnbr) (void)hipFree(m->d_tetnbr);
   if (m->d_bvh) (void)hipFree(m->d_bvh);
   if (m->d_perm) (void)hipFree(m->d_perm);
   if (m->d_inv_perm) (void)hipFree(m->d_inv_perm);
@@ -417,6 +429,7 @@ void mesh_free_device(tct_mesh* m) {
   m->d_faces = nullptr;
   m->d_bfaces = nullptr;
   m->d_tetxyz = nullptr;
+  m->d_tetnbr = nullptr;
   m->d_bvh = nullptr;
   m->d_perm = m->d_inv_perm = nullptr;
   m->d_counters = nullptr;

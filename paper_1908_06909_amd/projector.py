@@ -15,7 +15,7 @@ import torch
 
 from . import _lib
 from ._lib import (TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_GATHER, TCT_BP_SHADOW, call, lib, tct_cone,
-                   tct_range, tct_stats)
+                   tct_paper_stats, tct_range, tct_stats)
 
 
 def _stream(device) -> int:
@@ -192,6 +192,21 @@ class Projector:
              _ptr(out, torch.float32, self.mesh.device_index, self.nt, "xhat"), m, 1 if accumulate else 0,
              self._entry_ptr(use_cache), _stream(self.device))
         return out
+
+    def forward_paper(self, x: torch.Tensor, precision: int = 64, out: Optional[torch.Tensor] = None):
+        """The paper's own propagation (Moller-Trumbore with eps escalation,
+        Algorithms 1-2) in float32 or float64; returns (proj, stats dict).
+        Needs the entry cache.  Synchronises the stream."""
+        if self.entry is None:
+            raise ValueError("the paper-faithful walk needs the entry cache (Projector(cache_entry=True))")
+        if out is None:
+            out = torch.empty(self.geom.shape, dtype=torch.float32, device=self.device)
+        st = tct_paper_stats()
+        call("tct_forward_paper", self.mesh.handle, self.geom.handle,
+             _ptr(x, torch.float32, self.mesh.device_index, self.nt, "x"),
+             _ptr(out, torch.float32, self.mesh.device_index, self.geom.nrays, "proj"), self.entry.data_ptr(),
+             int(precision), C.byref(st), _stream(self.device))
+        return out, st.as_dict()
 
     _BP_MODES = {"atomic": TCT_BP_ATOMIC, "atomic_direct": TCT_BP_ATOMIC_DIRECT, "gather": TCT_BP_GATHER,
                  "shadow": TCT_BP_SHADOW}
