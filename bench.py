@@ -78,6 +78,9 @@ def parse():
                     help="time OS-SART sweeps with blocks of BLOCK consecutive angles instead")
     ap.add_argument("--paper-mode", action="store_true",
                     help="compare the paper's Moller-Trumbore propagation (float32, float64) with the exact walk")
+    ap.add_argument("--init-sweep", default="",
+                    help="comma-separated point counts: entry search vs walk time on random-point Delaunay meshes, "
+                         "one 1024x1024 projection each")
     ap.add_argument("--bp", default="atomic", choices=["atomic", "shadow", "atomic_direct", "gather"],
                     help="backprojection of the timed step")
     ap.add_argument("--json-extra", default=None)
@@ -124,6 +127,57 @@ def cpu_baseline(w, budget_s):
         "sample": f"every {k}-th ray ({len(ids)} rays, {segs} segments fwd+back) of the same workload; "
                   f"forward {t1 - t0:.1f}s, backprojection {t2 - t1:.1f}s; mesh build {build_s:.1f}s untimed",
     }
+
+
+def init_sweep_bench(args):
+    """Initialisation (boundary entry search) against propagation (the walk)
+    as the mesh grows: unstructured Delaunay meshes of random points in the
+    unit cube, one 1024 x 1024 projection each (the shape of the paper's
+    Section III-D study)."""
+    import torch
+
+    import paper_1908_06909_amd as tct
+    import synth
+
+    dev = torch.device("cuda:0")
+    cone = synth.Cone(4.0, 8.0, 1024, 1024, 2.0 / 1024, 2.0 / 1024)
+    rows = []
+    for n in [int(float(v)) for v in args.init_sweep.split(",")]:
+        t0 = time.time()
+        verts, tets = synth.delaunay_mesh(n, 1000 + n % 997)
+        t_gen = time.time() - t0
+        t0 = time.time()
+        mesh = tct.TetMesh(verts, tets, device=dev)
+        geom = tct.ConeGeometry(cone, np.array([0.3]), device=dev)
+        t_ingest = time.time() - t0
+        P = tct.Projector(mesh, geom, cache_entry=False)
+        x = torch.ones(mesh.nt, dtype=torch.float32, device=dev)
+        entry = torch.empty(geom.nrays, dtype=torch.int32, device=dev)
+        proj = torch.empty(geom.shape, dtype=torch.float32, device=dev)
+        P.compute_entry(entry)
+        P.entry = entry
+        P.forward(x, out=proj)
+        torch.cuda.synchronize()
+        mesh.stats(reset=True)
+        reps = max(1, args.steps)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        for _ in range(reps):
+            P.compute_entry(entry)
+        e[1].record()
+        for _ in range(reps):
+            P.forward(x, out=proj)
+        e[2].record()
+        torch.cuda.synchronize()
+        st = mesh.stats(reset=True)
+        rows.append({"points": n, "tets": mesh.nt, "boundary_faces": mesh.nboundary,
+                     "entry_ms": e[0].elapsed_time(e[1]) / reps, "walk_ms": e[1].elapsed_time(e[2]) / reps,
+                     "segments_per_ray": st["segments"] / max(1, st["rays"]),
+                     "host_delaunay_s": t_gen, "host_ingest_s": t_ingest})
+        print(json.dumps(rows[-1]), flush=True)
+        del P, mesh, geom, entry, proj, x
+    print(json.dumps({"metric": "entry search vs walk on Delaunay meshes, one 1024x1024 projection",
+                      "data": "synthetic", "rows": rows}))
 
 
 def paper_mode_bench(args):
@@ -310,6 +364,9 @@ def main():
         return
     if args.paper_mode:
         paper_mode_bench(args)
+        return
+    if args.init_sweep:
+        init_sweep_bench(args)
         return
 
     dev = torch.device("cuda:0")

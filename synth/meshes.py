@@ -1,4 +1,5 @@
-"""Kuhn-subdivided product-grid meshes, interior jitter and geometric grading.
+"""Kuhn-subdivided product-grid meshes, interior jitter and geometric grading;
+unstructured Delaunay meshes of random points.
 
 A product grid with node arrays X (nx+1), Y (ny+1), Z (nz+1) is cut into
 cells; every cell is split into the six Kuhn tetrahedra
@@ -136,3 +137,21 @@ def jitter_interior(verts, tets, dims, h, amplitude: float, seed: int, max_round
 def tet_centroids(verts, tets) -> np.ndarray:
     """Mean of the four vertices of each tetrahedron, float64."""
     return verts.astype(np.float64)[tets].mean(axis=1)
+
+
+def delaunay_mesh(n_points: int, seed: int, lo: float = -0.5, hi: float = 0.5):
+    """Delaunay tetrahedralisation of n_points uniform random points in the
+    cube [lo, hi]^3 (PCG64 seed), coordinates rounded to float32 first so the
+    triangulation is of the float32 points.  Unstructured, with the slivers a
+    Delaunay mesh of random points has; its boundary is the (convex) hull of
+    the points.  Returns (verts float32 [n][3], tets int32 [nt][4])."""
+    from scipy.spatial import Delaunay
+
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(lo, hi, size=(n_points, 3)).astype(np.float32)
+    tri = Delaunay(pts.astype(np.float64))
+    tets = np.ascontiguousarray(tri.simplices, dtype=np.int32)
+    vol = _signed_volumes6(pts.astype(np.float64), tets)
+    if np.any(vol == 0.0):
+        raise ValueError("degenerate Delaunay tetrahedron; choose another seed")
+    return pts, tets

@@ -24,6 +24,11 @@ def _case(name):
     if name == "kuhn8":
         w = synth.config(0)
         verts, tets, x, cone, angles = w.verts, w.tets, w.x, w.cone, w.angles
+    elif name == "delaunay":
+        verts, tets = synth.delaunay_mesh(3000, 2)
+        x = synth.uniform_random(len(tets), 8)
+        cone = synth.Cone(4.0, 8.0, 48, 40, 2.0 / 40, 2.0 / 40, 0.003, -0.002)
+        angles = synth.angles_for(6)
     else:
         (verts, tets), X, Z = synth.graded_mesh(24, 8, 1.05, 17)
         x = synth.sphere_phantom(verts, tets, 12)
@@ -38,7 +43,7 @@ def _case(name):
     return orc, P, x, xi
 
 
-@pytest.mark.parametrize("name", ["kuhn8", "graded24"])
+@pytest.mark.parametrize("name", ["kuhn8", "graded24", "delaunay"])
 @pytest.mark.parametrize("precision", [32, 64])
 def test_paper_mode_matches_oracle(name, precision):
     orc, P, x, xi = _case(name)

@@ -74,6 +74,12 @@ def case(name):
             du = 2.0 ** -5
             cone = synth.Cone(4.0, 8.0, 64, 64, du, du, du / 2, du / 2)
             w = synth.Workload("graded24", verts, tets, x, cone, synth.angles_for(12))
+        elif name == "delaunay":
+            # Unstructured: Delaunay mesh of 3000 random points (~20k tetrahedra with slivers).
+            verts, tets = synth.delaunay_mesh(3000, 2)
+            x = synth.uniform_random(len(tets), 8)
+            cone = synth.Cone(4.0, 8.0, 48, 40, 2.0 / 40, 2.0 / 40, 0.003, -0.002)
+            w = synth.Workload("delaunay3000", verts, tets, x, cone, synth.angles_for(6))
         elif name == "ragged":
             w = synth.jittered_kuhn(5, 7, 8, 37, 29, 5)
             w.cone = synth.Cone(4.0, 8.0, 37, 29, 0.08, 0.09, 0.013, -0.021)  # wider than the mesh shadow
@@ -415,3 +421,22 @@ def test_geometry_rejected_when_mesh_not_between_source_and_detector():
     with pytest.raises(tct._lib.TctError) as e:
         tct.Projector(m, g)
     assert e.value.status == -6
+
+
+def test_delaunay_sequences_projection_and_backprojections():
+    """Unstructured mesh (random-point Delaunay, slivers included): sequences
+    bit-exact, forward and all backprojections within tolerance."""
+    c = case("delaunay")
+    ids = np.arange(c.orc.nrays)
+    compare_traces(c.P.trace(ids), c.orc.trace(ids), ray_lengths(c, ids))
+    xi = c.x_internal(c.w.x)
+    got = c.P.forward(xi).cpu().numpy().ravel()
+    ref = c.orc.forward(c.w.x)
+    assert_within(got, ref, forward_tolerance(c, c.w.x), "delaunay forward")
+    y = np.random.default_rng(7).uniform(-1, 1, c.orc.nrays).astype(f32)
+    ref_bp = c.orc.backproject(y)
+    tol = _bp_tolerance(c, y)
+    for mode in ("atomic", "gather", "shadow"):
+        bp = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode)).astype(np.float64)
+        assert_within(bp, ref_bp, tol, f"delaunay backprojection {mode}")
+    check_stats(c.mesh)

@@ -220,6 +220,29 @@ def test_oracle_vs_brute_force_clipping_jittered():
             assert abs(pos[t] - ref[t]) <= 1e-12 * max(1.0, sum(ref.values()))
 
 
+def test_oracle_vs_brute_force_clipping_delaunay():
+    """Unstructured mesh (Delaunay of 40 random points, slivers included)."""
+    verts, tets = synth.delaunay_mesh(40, 11)
+    m = oracle.OracleMesh(verts, tets)
+    rng = np.random.default_rng(2025)
+    rays = _random_generic_rays(rng, 60)
+    S, P, U, V = (np.array([r[k] for r in rays]) for k in range(4))
+    paths = oracle.oracle.trace_rays(m, S, P, U, V)
+    hits = 0
+    for (s, p, _, _), (tt, ll) in zip(rays, paths):
+        ref = brute_force_lengths(verts, tets, s, p)
+        got = {}
+        for t, l in zip(tt, ll):
+            assert t not in got, "tetrahedron visited twice"
+            got[int(t)] = l
+        pos = {t: l for t, l in got.items() if l > 1e-12}
+        assert set(pos) == set(ref)
+        hits += len(ref) > 0
+        for t in ref:
+            assert abs(pos[t] - ref[t]) <= 1e-12 * max(1.0, sum(ref.values()))
+    assert hits >= 20
+
+
 def _trace_custom(m, rays):
     S, P, U, V = (np.array([r[k] for r in rays], f32) for k in range(4))
     return oracle.oracle.trace_rays(m, S, P, U, V)
