@@ -71,6 +71,7 @@ struct ShadowArgs {
   float u0, inv_du;  // pixel column coordinate of detector abscissa u: (u - u0) * inv_du
   float v0, inv_dv;
   float margin;      // pixels added around each shadow
+  float du, dv;      // pixel pitch: local coordinates are (i - i0) du, (j - j0) dv
   float eps_p;       // bound on the detector-plane distance between a pixel's ray and the pixel centre
   int* dirty_count;  // items (chunk * nt + t) left to the exact pass
   int* dirty;
@@ -210,31 +211,67 @@ __device__ __forceinline__ void store_result(const ShadowArgs& A, int chunk, int
 
 // ---------------------------------------------------------------- fast pass
 
-template <bool kLdsTables>
-__global__ __launch_bounds__(kShadowThreads) void shadow_fast_kernel(ShadowArgs A) {
-  __shared__ float s_ut[kLdsTables ? kShadowLdsTable : 1];
-  __shared__ float s_vt[kLdsTables ? kShadowLdsTable : 1];
+// Edge e joins local vertices (p, q), p < q: 0 = (0,1), 1 = (0,2), 2 = (0,3),
+// 3 = (1,2), 4 = (1,3), 5 = (2,3).  Face f is opposite vertex f; its outward
+// edge values are those listed in entry_face.
+constexpr int kEdgeP[6] = {0, 0, 0, 1, 1, 2};
+constexpr int kEdgeQ[6] = {1, 2, 3, 2, 3, 3};
+
+// Largest (smallest) outward edge value of each face: the face is the entry
+// (exit) face of the ray iff this is negative (positive).
+__device__ __forceinline__ void face_max(const float* E, float* g) {
+  g[0] = fmaxf(fmaxf(E[3], E[5]), -E[4]);
+  g[1] = fmaxf(fmaxf(E[2], -E[5]), -E[1]);
+  g[2] = fmaxf(fmaxf(E[0], E[4]), -E[2]);
+  g[3] = fmaxf(fmaxf(E[1], -E[3]), -E[0]);
+}
+__device__ __forceinline__ void face_min(const float* E, float* g) {
+  g[0] = fminf(fminf(E[3], E[5]), -E[4]);
+  g[1] = fminf(fminf(E[2], -E[5]), -E[1]);
+  g[2] = fminf(fminf(E[0], E[4]), -E[2]);
+  g[3] = fminf(fminf(E[1], -E[3]), -E[0]);
+}
+
+// One lane per tetrahedron and angle chunk.  Per angle the six 2-D edge
+// values are affine in the pixel position, E_e = C_e + x A_e + y B_e in
+// coordinates local to the shadow's first pixel, evaluated as one fused
+// multiply-add per pixel on a per-row value.  A pixel is decided when the
+// smallest over faces of the largest outward edge value is certainly
+// positive (no entry face: miss) or, for a hit, certainly negative with an
+// exit face whose smallest value is certainly positive; anything else takes
+// the per-edge route (float64 3-D values, then the exact pass).
+template <bool kLdsTable>
+__global__ __launch_bounds__(kShadowThreads, 4) void shadow_fast_kernel(ShadowArgs A) {
+  // Face planes of each lane's tetrahedron, float64: (n_x, n_y) and
+  // (n_z, (a_f - S) . n_f) for face f through vertex a_f.
+  __shared__ double2 s_plane[4][2][kShadowThreads];
+  __shared__ float s_ut[kLdsTable ? kShadowLdsTable : 1];
   const int nu = A.G.nu, nv = A.G.nv;
-  if constexpr (kLdsTables) {
+  if constexpr (kLdsTable) {
     for (int k = threadIdx.x; k < nu; k += kShadowThreads) s_ut[k] = A.G.ut[k];
-    for (int k = threadIdx.x; k < nv; k += kShadowThreads) s_vt[k] = A.G.vt[k];
     __syncthreads();
   }
-  const float* ut = kLdsTables ? s_ut : A.G.ut;
-  const float* vt = kLdsTables ? s_vt : A.G.vt;
-
+  const float* ut = kLdsTable ? s_ut : A.G.ut;
+  const float* vt = A.G.vt;
   const int nt = A.M.nt;
-  const int t = blockIdx.x * kShadowThreads + threadIdx.x;
+  const int lane = threadIdx.x;
+  const int t = blockIdx.x * kShadowThreads + lane;
   const int chunk = blockIdx.y;
   const int a_begin = A.a0 + chunk * A.chunk_len;
   const int a_end = min(A.a0 + A.na, a_begin + A.chunk_len);
   ShadowStats st;
   if (t < nt) {
     const float4* tq = A.M.tetxyz + 3 * (size_t)t;
-    float4 q0 = tq[0], q1 = tq[1], q2 = tq[2];
-    // Vertices in positive orientation: det[v1 - v0, v2 - v0, v3 - v0] > 0.
-    float3 v[4] = {make_float3(q0.x, q0.y, q0.z), make_float3(q0.w, q1.x, q1.y), make_float3(q1.z, q1.w, q2.x),
-                   make_float3(q2.y, q2.z, q2.w)};
+    // Face normals (angle independent), vertices in increasing order.
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int ia = f == 0 ? 1 : 0, ib = f <= 1 ? 2 : 1, ic = f == 3 ? 2 : 3;
+      const float3 pa = tet_vertex(tq, ia), pb = tet_vertex(tq, ib), pc = tet_vertex(tq, ic);
+      double bx = (double)pb.x - pa.x, by = (double)pb.y - pa.y, bz = (double)pb.z - pa.z;
+      double cx = (double)pc.x - pa.x, cy = (double)pc.y - pa.y, cz = (double)pc.z - pa.z;
+      s_plane[f][0][lane] = make_double2(by * cz - bz * cy, bz * cx - bx * cz);
+      s_plane[f][1][lane] = make_double2(bx * cy - by * cx, 0.0);
+    }
     double acc = 0.0;
     bool deferred = false;
 #pragma unroll 1
@@ -242,115 +279,124 @@ __global__ __launch_bounds__(kShadowThreads) void shadow_fast_kernel(ShadowArgs 
       FrameD F = load_frame(A.G.frame, a);
       double al[4], be[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) project_vertex(F, v[k], al[k], be[k]);
+      for (int k = 0; k < 4; ++k) project_vertex(F, tet_vertex(tq, k), al[k], be[k]);
       int i0, i1, j0, j1;
       if (!shadow_box(A, al, be, i0, i1, j0, j1)) continue;
       // Local detector coordinates around the pixel centre (i0, j0).
       const float ao = ut[i0], bo = vt[j0];
       float xk[4], yk[4];
-      float Lb = fmaxf(ut[i1] - ao, vt[j1] - bo);
+      float Lb = fmaxf(fmaxf(ut[i1] - ao, vt[j1] - bo), fmaxf((float)(i1 - i0) * A.du, (float)(j1 - j0) * A.dv));
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         xk[k] = (float)(al[k] - (double)ao);
         yk[k] = (float)(be[k] - (double)bo);
         Lb = fmaxf(Lb, fmaxf(fabsf(xk[k]), fabsf(yk[k])));
       }
-      // E'_pq = (x_p - x)(y_q - y) - (y_p - y)(x_q - x) evaluated in float32
-      // from rounded local coordinates differs from its exact value at the
-      // pixel centre by at most 48 u Lb^2; the ray meets the plane within
-      // eps_p of the centre, which moves E' by at most 4 eps_p Lb.
+      // E'_pq = (x_p - x)(y_q - y) - (y_p - y)(x_q - x) differs from its
+      // exact value at the pixel centre by at most 34 u Lb^2 for the
+      // rounding of the local coordinates (vertices and pixel) and of the
+      // affine evaluation; the ray meets the plane within eps_p of the
+      // centre, which moves E' by at most 4 eps_p Lb.
       const float bound = fmaf(64.0f * kUnit * Lb, Lb, fmaf(4.5f * A.eps_p, Lb, kShadowAbs));
       const float sg = F.hN > 0.0 ? 1.0f : -1.0f;
-      // Face planes for the chord: n_f and (a_f - S) . n_f in float64.
-      double nfx[4], nfy[4], nfz[4], numf[4];
+      // E = sg E' = cC + kx cA + y cB with kx = i - i0 and y = (j - j0) dv.
+      float cA[6], cB[6], cC[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        const int p = kEdgeP[e], q = kEdgeQ[e];
+        cA[e] = sg * ((yk[p] - yk[q]) * A.du);
+        cB[e] = sg * (xk[q] - xk[p]);
+        cC[e] = sg * fmaf(xk[p], yk[q], -(yk[p] * xk[q]));
+      }
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        // Face f is opposite vertex f; take its vertices in increasing order.
-        const int ia = f == 0 ? 1 : 0, ib = f <= 1 ? 2 : 1, ic = f == 3 ? 2 : 3;
-        double bx = (double)v[ib].x - v[ia].x, by = (double)v[ib].y - v[ia].y, bz = (double)v[ib].z - v[ia].z;
-        double cx = (double)v[ic].x - v[ia].x, cy = (double)v[ic].y - v[ia].y, cz = (double)v[ic].z - v[ia].z;
-        nfx[f] = by * cz - bz * cy;
-        nfy[f] = bz * cx - bx * cz;
-        nfz[f] = bx * cy - by * cx;
-        numf[f] = ((double)v[ia].x - F.Sx) * nfx[f] + ((double)v[ia].y - F.Sy) * nfy[f] +
-                  ((double)v[ia].z - F.Sz) * nfz[f];
+        const float3 pa = tet_vertex(tq, f == 0 ? 1 : 0);
+        const double2 n0 = s_plane[f][0][lane];
+        double2 n1 = s_plane[f][1][lane];
+        n1.y = ((double)pa.x - F.Sx) * n0.x + ((double)pa.y - F.Sy) * n0.y + ((double)pa.z - F.Sz) * n1.x;
+        s_plane[f][1][lane] = n1;
       }
       const float* yrow = A.proj + (size_t)a * nv * nu;
 #pragma unroll 1
       for (int j = j0; j <= j1 && !deferred; ++j) {
         const float vv = vt[j];
-        const float y = vv - bo;
-        float Yk[4];
+        const float y = (float)(j - j0) * A.dv;
+        const float* yr = yrow + (size_t)j * nu;
+        float R[6];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) Yk[k] = yk[k] - y;
+        for (int e = 0; e < 6; ++e) R[e] = fmaf(y, cB[e], cC[e]);
 #pragma unroll 1
         for (int i = i0; i <= i1; ++i) {
+          // Issued first so that their latency overlaps the classification.
+          const float yv = yr[i];
           const float uu = ut[i];
-          const float x = uu - ao;
-          float Xk[4];
+          const float kx = (float)(i - i0);
+          float E[6];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) Xk[k] = xk[k] - x;
-          int pos = 0, neg = 0;
+          for (int e = 0; e < 6; ++e) E[e] = fmaf(kx, cA[e], R[e]);
+          float g[4];
+          face_max(E, g);
+          const float m = fminf(fminf(g[0], g[1]), fminf(g[2], g[3]));
+          if (m > bound) continue;
+          float h[4];
+          face_min(E, h);
+          const float M = fmaxf(fmaxf(h[0], h[1]), fmaxf(h[2], h[3]));
+          int fe = 3, fx = 3;
+          fe = g[2] == m ? 2 : fe;
+          fe = g[1] == m ? 1 : fe;
+          fe = g[0] == m ? 0 : fe;
+          fx = h[2] == M ? 2 : fx;
+          fx = h[1] == M ? 1 : fx;
+          fx = h[0] == M ? 0 : fx;
+          fx = (m < -bound && M > bound) ? fx : -1;
+          const float3 P = pixel_point(F.f, uu, vv);
+          const double dx = (double)P.x - F.Sx, dy = (double)P.y - F.Sy, dz = (double)P.z - F.Sz;
+          if (fx < 0) {
+            // Per-edge route: certain float signs, float64 3-D values for
+            // the rest, the exact pass for what float64 cannot decide.
+            int pos = 0, neg = 0;
 #pragma unroll
-          for (int e = 0; e < 6; ++e) {
-            const int p = e < 3 ? 0 : (e < 5 ? 1 : 2);
-            const int q = e < 3 ? e + 1 : (e < 5 ? e - 1 : 3);
-            float E = sg * fmaf(Xk[p], Yk[q], -(Yk[p] * Xk[q]));
-            pos |= (E > bound) << e;
-            neg |= (E < -bound) << e;
-          }
-          int unk = 0x3f & ~(pos | neg);
-          float3 P = make_float3(0.f, 0.f, 0.f);
-          double dx = 0.0, dy = 0.0, dz = 0.0;
-          bool have_p = false;
-          if (unk) {
-            P = pixel_point(F.f, uu, vv);
-            dx = (double)P.x - F.Sx;
-            dy = (double)P.y - F.Sy;
-            dz = (double)P.z - F.Sz;
-            have_p = true;
-            float3 df = f3sub(P, F.S);
-            float dinf = fmaxf(fabsf(df.x), fmaxf(fabsf(df.y), fabsf(df.z)));
-            while (unk) {
-              int e = __ffs(unk) - 1;
-              unk &= unk - 1;
-              int pe = (0x211000 >> (4 * e)) & 3, qe = (0x332321 >> (4 * e)) & 3;
-              int s = edge_sign_fp64(F, dx, dy, dz, dinf, tet_vertex(tq, pe), tet_vertex(tq, qe), nullptr);
-              st.fp64++;
-              if (s == 0) {
-                deferred = true;
-                break;
-              }
-              pos |= (s > 0) << e;
-              neg |= (s < 0) << e;
+            for (int e = 0; e < 6; ++e) {
+              pos |= (E[e] > bound) << e;
+              neg |= (E[e] < -bound) << e;
             }
-            if (deferred) break;
+            int unk = 0x3f & ~(pos | neg);
+            if (unk) {
+              const float3 df = f3sub(P, F.S);
+              const float dinf = fmaxf(fabsf(df.x), fmaxf(fabsf(df.y), fabsf(df.z)));
+              while (unk) {
+                const int e = __ffs(unk) - 1;
+                unk &= unk - 1;
+                const int pe = (0x211000 >> (4 * e)) & 3, qe = (0x332321 >> (4 * e)) & 3;
+                const int s = edge_sign_fp64(F, dx, dy, dz, dinf, tet_vertex(tq, pe), tet_vertex(tq, qe), nullptr);
+                st.fp64++;
+                if (s == 0) {
+                  deferred = true;
+                  break;
+                }
+                pos |= (s > 0) << e;
+                neg |= (s < 0) << e;
+              }
+              if (deferred) break;
+            }
+            fe = entry_face(neg, pos);
+            if (fe < 0) continue;
+            fx = entry_face(pos, neg);
+            if (fx < 0) continue;  // cannot happen for a valid tetrahedron
           }
-          const int fe = entry_face(neg, pos);
-          if (fe < 0) continue;
-          const int fx = entry_face(pos, neg);
-          if (fx < 0) continue;  // cannot happen for a valid tetrahedron
           st.hits++;
-          if (!have_p) {
-            P = pixel_point(F.f, uu, vv);
-            dx = (double)P.x - F.Sx;
-            dy = (double)P.y - F.Sy;
-            dz = (double)P.z - F.Sz;
-          }
-          double den[4];
-#pragma unroll
-          for (int f = 0; f < 4; ++f) den[f] = fma(dx, nfx[f], fma(dy, nfy[f], dz * nfz[f]));
-          const double de = fe == 0 ? den[0] : fe == 1 ? den[1] : fe == 2 ? den[2] : den[3];
-          const double ne = fe == 0 ? numf[0] : fe == 1 ? numf[1] : fe == 2 ? numf[2] : numf[3];
-          const double dxx = fx == 0 ? den[0] : fx == 1 ? den[1] : fx == 2 ? den[2] : den[3];
-          const double nx = fx == 0 ? numf[0] : fx == 1 ? numf[1] : fx == 2 ? numf[2] : numf[3];
+          const double2 e0 = s_plane[fe][0][lane], e1 = s_plane[fe][1][lane];
+          const double2 x0 = s_plane[fx][0][lane], x1 = s_plane[fx][1][lane];
+          const double de = fma(dx, e0.x, fma(dy, e0.y, dz * e1.x));
+          const double dxx = fma(dx, x0.x, fma(dy, x0.y, dz * x1.x));
           // t_x - t_e = (n_x d_e - n_e d_x) / (d_x d_e); the float64
           // numerator keeps the cancellation harmless.
-          const double num = nx * de - ne * dxx;
-          const double dd = dx * dx + dy * dy + dz * dz;
-          float L = (float)num / (float)(dxx * de) * sqrtf((float)dd);
+          const double num = fma(x1.y, de, -(e1.y * dxx));
+          const float3 df = f3sub(P, F.S);
+          const float dn = __builtin_amdgcn_sqrtf(fmaf(df.x, df.x, fmaf(df.y, df.y, df.z * df.z)));
+          float L = (float)num * dn * __builtin_amdgcn_rcpf((float)(dxx * de));
           L = fmaxf(L, 0.f);
-          acc = fma((double)L, (double)yrow[(size_t)j * nu + i], acc);
+          acc = fma((double)L, (double)yv, acc);
         }
       }
     }
@@ -539,7 +585,15 @@ tct_status backproject_shadow(const tct_mesh* m, const tct_geom* g, const float*
         eps = std::max(eps, u * err * (1.0 + tanv) / umin);
       }
   }
-  A.eps_p = (float)(1.25 * eps);
+  // The pixel tables are float32 roundings of affine values: the local
+  // coordinates (i - i0) du used by the fast pass differ from the tables'
+  // differences by at most 2u max|table| (the product's rounding is in the
+  // kernel's bound).
+  const double tmax = std::max(std::max(std::fabs((double)g->ut.front()), std::fabs((double)g->ut.back())),
+                               std::max(std::fabs((double)g->vt.front()), std::fabs((double)g->vt.back())));
+  A.eps_p = (float)(1.25 * (eps + 2.0 * u * (tmax + std::max(c.du, c.dv))));
+  A.du = (float)c.du;
+  A.dv = (float)c.dv;
   R += std::max(std::max(std::fabs((double)g->ut.front()), std::fabs((double)g->ut.back())),
                 std::max(std::fabs((double)g->vt.front()), std::fabs((double)g->vt.back())));
   // Shadow margin: rounding of the pixel points and of the projected vertices
