@@ -78,9 +78,11 @@ def parse():
                     help="time OS-SART sweeps with blocks of BLOCK consecutive angles instead")
     ap.add_argument("--paper-mode", action="store_true",
                     help="compare the paper's Moller-Trumbore propagation (float32, float64) with the exact walk")
+    ap.add_argument("--init-mesh", default="delaunay", choices=["delaunay", "kuhn"],
+                    help="with --init-sweep: mesh family (sizes are points, or n for Kuhn n^3)")
     ap.add_argument("--init-sweep", default="",
-                    help="comma-separated point counts: entry search vs walk time on random-point Delaunay meshes, "
-                         "one 1024x1024 projection each")
+                    help="comma-separated mesh sizes (see --init-mesh): entry search (BVH and R*-tree) vs walk "
+                         "time, one 1024x1024 projection each")
     ap.add_argument("--bp", default="atomic", choices=["atomic", "shadow", "atomic_direct", "gather"],
                     help="backprojection of the timed step")
     ap.add_argument("--json-extra", default=None)
@@ -131,9 +133,12 @@ def cpu_baseline(w, budget_s):
 
 def init_sweep_bench(args):
     """Initialisation (boundary entry search) against propagation (the walk)
-    as the mesh grows: unstructured Delaunay meshes of random points in the
-    unit cube, one 1024 x 1024 projection each (the shape of the paper's
-    Section III-D study)."""
+    as the mesh grows, one 1024 x 1024 projection each (the shape of the
+    paper's Section III-D study).  Meshes: Delaunay tetrahedralisations of
+    random points in the unit cube (few boundary faces), or triangulated
+    regular grids (Kuhn n^3, 12 n^2 boundary faces, the paper's benchmark
+    meshes).  The entry search is timed through the boundary BVH and through
+    the R*-tree of Section II-E; both must return the same faces."""
     import torch
 
     import paper_1908_06909_amd as tct
@@ -144,40 +149,55 @@ def init_sweep_bench(args):
     rows = []
     for n in [int(float(v)) for v in args.init_sweep.split(",")]:
         t0 = time.time()
-        verts, tets = synth.delaunay_mesh(n, 1000 + n % 997)
+        if args.init_mesh == "kuhn":
+            X = synth.kuhn_nodes(n)
+            verts, tets = synth.kuhn_mesh(X, X, X)
+        else:
+            verts, tets = synth.delaunay_mesh(n, 1000 + n % 997)
         t_gen = time.time() - t0
         t0 = time.time()
-        mesh = tct.TetMesh(verts, tets, device=dev)
+        mesh = tct.TetMesh(verts, tets, device=dev, rstar=True)
         geom = tct.ConeGeometry(cone, np.array([0.3]), device=dev)
         t_ingest = time.time() - t0
         P = tct.Projector(mesh, geom, cache_entry=False)
         x = torch.ones(mesh.nt, dtype=torch.float32, device=dev)
         entry = torch.empty(geom.nrays, dtype=torch.int32, device=dev)
+        entry_r = torch.empty(geom.nrays, dtype=torch.int32, device=dev)
         proj = torch.empty(geom.shape, dtype=torch.float32, device=dev)
         P.compute_entry(entry)
+        P.compute_entry(entry_r, method="rstar")
         P.entry = entry
         P.forward(x, out=proj)
         torch.cuda.synchronize()
+        agree = bool(torch.equal(entry, entry_r))
         mesh.stats(reset=True)
         reps = max(1, args.steps)
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         e[0].record()
         for _ in range(reps):
             P.compute_entry(entry)
         e[1].record()
         for _ in range(reps):
-            P.forward(x, out=proj)
+            P.compute_entry(entry_r, method="rstar")
         e[2].record()
+        for _ in range(reps):
+            P.forward(x, out=proj)
+        e[3].record()
         torch.cuda.synchronize()
         st = mesh.stats(reset=True)
-        rows.append({"points": n, "tets": mesh.nt, "boundary_faces": mesh.nboundary,
-                     "entry_ms": e[0].elapsed_time(e[1]) / reps, "walk_ms": e[1].elapsed_time(e[2]) / reps,
-                     "segments_per_ray": st["segments"] / max(1, st["rays"]),
-                     "host_delaunay_s": t_gen, "host_ingest_s": t_ingest})
+        walk_rays = st["rays"] - 2 * reps * geom.nrays  # the entry passes count their rays too
+        rows.append({"mesh": args.init_mesh, "size": n, "tets": mesh.nt, "boundary_faces": mesh.nboundary,
+                     "rstar_height": mesh.rstar()["height"],
+                     "entry_bvh_ms": e[0].elapsed_time(e[1]) / reps, "entry_rstar_ms": e[1].elapsed_time(e[2]) / reps,
+                     "walk_ms": e[2].elapsed_time(e[3]) / reps, "rstar_equals_bvh": agree,
+                     "segments_per_ray": st["segments"] / max(1, walk_rays),
+                     "host_generate_s": t_gen, "host_ingest_s": t_ingest})
         print(json.dumps(rows[-1]), flush=True)
-        del P, mesh, geom, entry, proj, x
-    print(json.dumps({"metric": "entry search vs walk on Delaunay meshes, one 1024x1024 projection",
+        del P, mesh, geom, entry, entry_r, proj, x
+    print(json.dumps({"metric": "entry search (BVH and R*-tree) vs walk, one 1024x1024 projection",
                       "data": "synthetic", "rows": rows}))
+    if not all(r["rstar_equals_bvh"] for r in rows):
+        sys.exit(1)
 
 
 def paper_mode_bench(args):

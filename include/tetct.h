@@ -102,6 +102,7 @@ typedef struct {
 /* Flags for tct_mesh_create. */
 #define TCT_MESH_NO_REORDER 1u /* keep the user's tetrahedron order as the internal order */
 #define TCT_MESH_HOST_ONLY 2u  /* build and validate on the host only; no device upload (compute calls fail) */
+#define TCT_MESH_RSTAR 4u      /* also build the R*-tree over the boundary faces (tct_entry_rstar) */
 
 /* Build a mesh from nodes and elements (Section II-B).
  *   verts  host float [nv][3]  node coordinates
@@ -118,6 +119,24 @@ typedef struct {
  * Section II-E).  On error *out is set to NULL. */
 tct_status tct_mesh_create(const float* verts, int32_t nv, const int32_t* tets, int32_t nt, const int32_t* nbrs,
                            uint32_t flags, int device, tct_mesh** out);
+
+/* Boundary faces in entry-id order (the ids tct_entry returns).
+ *   xyz    host float [nboundary][3][3]  vertices, ordered so that (p1 - p0) x (p2 - p0) points out of the mesh
+ *   owner  host int32 [nboundary]        user id of the tetrahedron the face belongs to
+ * Either pointer may be NULL. */
+tct_status tct_mesh_boundary(const tct_mesh* m, float* xyz, int32_t* owner);
+
+/* The R*-tree built with TCT_MESH_RSTAR (Section II-E: nodes of 4 to 10
+ * entries; R* insertion rules with forced reinsertion), flattened in
+ * depth-first preorder: an interior node's first child is the next node,
+ * skip is the node after its subtree (-1 at the end).
+ *   nnodes, nlist, height  host int32 out: node count, leaf-list length, levels (leaves included)
+ *   box    host float [nnodes][6]  lo xyz, hi xyz (face boxes padded outward)
+ *   link   host int32 [nnodes][2]  skip, leaf field (-1 interior; else first * 16 + count into list)
+ *   list   host int32 [nlist]      boundary-face ids of the leaves
+ * Call with NULL arrays to get the sizes.  TCT_E_ARG if the mesh has no R*-tree. */
+tct_status tct_mesh_rstar(const tct_mesh* m, int32_t* nnodes, int32_t* nlist, int32_t* height, float* box,
+                          int32_t* link, int32_t* list);
 
 /* Sizes: node count, tetrahedron count, boundary faces, device bytes held. Any pointer may be NULL. */
 tct_status tct_mesh_counts(const tct_mesh* m, int32_t* nv, int32_t* nt, int32_t* nboundary, int64_t* device_bytes);
@@ -159,6 +178,12 @@ void tct_geom_destroy(tct_geom* g);
  * array can be passed to the operators below to skip the search (it depends
  * only on the mesh and the geometry). */
 tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s);
+
+/* The same entry faces found through the R*-tree of Section II-E instead of
+ * the bounding-volume hierarchy (the mesh must be created with
+ * TCT_MESH_RSTAR, else TCT_E_ARG).  The result is identical: the exact entry
+ * test admits one face per ray. */
+tct_status tct_entry_rstar(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s);
 
 /* Forward projection b_j = sum_i a_ij x_i (Eq. 2).
  *   x     device float [nt], internal order

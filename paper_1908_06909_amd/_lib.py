@@ -28,6 +28,7 @@ STATUS = {
 
 TCT_MESH_NO_REORDER = 1
 TCT_MESH_HOST_ONLY = 2
+TCT_MESH_RSTAR = 4
 TCT_BP_ATOMIC = 0
 TCT_BP_GATHER = 1
 TCT_BP_ATOMIC_DIRECT = 2
@@ -72,6 +73,8 @@ _SIGS = {
     "tct_mesh_create": (C.c_int, [_P, C.c_int32, _P, C.c_int32, _P, C.c_uint32, C.c_int, C.POINTER(_P)]),
     "tct_mesh_counts": (C.c_int, [_P, _P, _P, _P, _P]),
     "tct_mesh_permutation": (C.c_int, [_P, _P]),
+    "tct_mesh_boundary": (C.c_int, [_P, _P, _P]),
+    "tct_mesh_rstar": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "tct_mesh_neighbors": (C.c_int, [_P, _P]),
     "tct_mesh_to_internal": (C.c_int, [_P, _P, _P, _P]),
     "tct_mesh_to_user": (C.c_int, [_P, _P, _P, _P]),
@@ -82,6 +85,7 @@ _SIGS = {
     "tct_geom_frame": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "tct_geom_destroy": (None, [_P]),
     "tct_entry": (C.c_int, [_P, _P, _P, _P]),
+    "tct_entry_rstar": (C.c_int, [_P, _P, _P, _P]),
     "tct_forward": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "tct_backproject": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, _P, _P]),
     "tct_trace": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),

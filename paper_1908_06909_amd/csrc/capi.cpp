@@ -92,6 +92,45 @@ tct_status tct_mesh_counts(const tct_mesh* m, int32_t* nv, int32_t* nt, int32_t*
   return TCT_OK;
 }
 
+tct_status tct_mesh_boundary(const tct_mesh* m, float* xyz, int32_t* owner) {
+  if (!m) {
+    set_error("null mesh");
+    return TCT_E_ARG;
+  }
+  if (xyz) std::memcpy(xyz, m->bface_xyz.data(), sizeof(float) * m->bface_xyz.size());
+  if (owner) std::memcpy(owner, m->bface_owner.data(), sizeof(int32_t) * m->bface_owner.size());
+  return TCT_OK;
+}
+
+tct_status tct_mesh_rstar(const tct_mesh* m, int32_t* nnodes, int32_t* nlist, int32_t* height, float* box,
+                          int32_t* link, int32_t* list) {
+  if (!m) {
+    set_error("null mesh");
+    return TCT_E_ARG;
+  }
+  if (!m->has_rstar) {
+    set_error("tct_mesh_rstar: mesh created without TCT_MESH_RSTAR");
+    return TCT_E_ARG;
+  }
+  if (nnodes) *nnodes = (int32_t)m->rstar_nodes.size();
+  if (nlist) *nlist = (int32_t)m->rstar_list.size();
+  if (height) *height = m->rstar_height;
+  for (size_t i = 0; i < m->rstar_nodes.size(); ++i) {
+    const tct::BvhNode& nd = m->rstar_nodes[i];
+    if (box)
+      for (int k = 0; k < 3; ++k) {
+        box[6 * i + k] = nd.lo[k];
+        box[6 * i + 3 + k] = nd.hi[k];
+      }
+    if (link) {
+      link[2 * i] = nd.skip;
+      link[2 * i + 1] = nd.leaf;
+    }
+  }
+  if (list) std::memcpy(list, m->rstar_list.data(), sizeof(int32_t) * m->rstar_list.size());
+  return TCT_OK;
+}
+
 tct_status tct_mesh_permutation(const tct_mesh* m, int32_t* internal_to_user) {
   if (!m || !internal_to_user) {
     set_error("null argument");
@@ -223,6 +262,22 @@ tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_s
   DeviceGuard dg(m->device);
   return launch_pixel_walk(kModeEntry, m, g, 0, g->na, nullptr, nullptr, nullptr, entry, nullptr, nullptr, nullptr,
                            nullptr, default_tile_u(), (hipStream_t)s);
+}
+
+tct_status tct_entry_rstar(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!entry) {
+    set_error("tct_entry_rstar: null output");
+    return TCT_E_ARG;
+  }
+  if (!m->has_rstar) {
+    set_error("tct_entry_rstar: mesh created without TCT_MESH_RSTAR");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return launch_pixel_walk(kModeEntryRstar, m, g, 0, g->na, nullptr, nullptr, nullptr, entry, nullptr, nullptr,
+                           nullptr, nullptr, default_tile_u(), (hipStream_t)s);
 }
 
 namespace {

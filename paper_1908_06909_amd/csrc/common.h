@@ -53,6 +53,10 @@ struct MeshView {
   // det[v1 - v0, v2 - v0, v3 - v0] > 0.
   const float4* tetxyz;
   const int32_t* tetnbr;  // [nt][4] neighbour across the face opposite tetxyz vertex k, -1 = boundary
+  // R*-tree over the boundary faces in the same preorder node format, leaf
+  // field first * 16 + count into rstar_faces (null when not built).
+  const BvhNode* rstar;
+  const int32_t* rstar_faces;
 };
 
 // Cone-beam frames: frame[12 a + 0..11] = S, D, U, V of angle a.
@@ -101,10 +105,18 @@ struct tct_mesh {
   float4* d_tetxyz = nullptr;
   int32_t* d_tetnbr = nullptr;
   tct::BvhNode* d_bvh = nullptr;
+  tct::BvhNode* d_rstar = nullptr;
+  int32_t* d_rstar_faces = nullptr;
   int32_t* d_perm = nullptr;
   int32_t* d_inv_perm = nullptr;
   unsigned long long* d_counters = nullptr;
   int nbvh = 0;
+  bool has_rstar = false;
+  std::vector<tct::BvhNode> rstar_nodes;  // host copy of the R*-tree (preorder)
+  std::vector<int32_t> rstar_list;        // its leaf face ids
+  int rstar_height = 0;
+  std::vector<float> bface_xyz;           // [nb][3][3] boundary faces in entry-id order
+  std::vector<int32_t> bface_owner;       // [nb] user owner tetrahedron
   int64_t device_bytes = 0;
   tct::MeshView view() const {
     tct::MeshView v;
@@ -117,6 +129,8 @@ struct tct_mesh {
     v.counters = d_counters;
     v.tetxyz = d_tetxyz;
     v.tetnbr = d_tetnbr;
+    v.rstar = d_rstar;
+    v.rstar_faces = d_rstar_faces;
     v.extent = 0.f;
     for (int k = 0; k < 3; ++k) v.extent = std::max(v.extent, std::max(std::fabs(lo[k]), std::fabs(hi[k])));
     return v;

@@ -14,6 +14,7 @@ enum WalkMode {
   kModeTrace = 5,
   kModeGatherFill = 6,
   kModeBackDirect = 7,  // backprojection with one global atomic per segment
+  kModeEntryRstar = 8,  // entry search through the R*-tree
 };
 
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,

@@ -13,6 +13,7 @@
 #include "common.h"
 #include "exact.h"
 #include "kernels.h"
+#include "rstar.h"
 
 namespace tct {
 
@@ -326,6 +327,30 @@ tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32
     bvh_build(items, 0, nb, 1e-4f * ext + 1e-30f, nodes, order);
     for (auto& nd : nodes)
       if (nd.skip >= (int)nodes.size()) nd.skip = -1;
+    // Boundary faces in entry-id order, and the R*-tree over them when asked.
+    m->bface_xyz.resize(9 * (size_t)nb);
+    m->bface_owner.resize(nb);
+    std::vector<float> flo(3 * (size_t)nb), fhi(3 * (size_t)nb);
+    for (int j = 0; j < nb; ++j) {
+      const int b = order[j];
+      for (int sl = 0; sl < 3; ++sl)
+        for (int k = 0; k < 3; ++k) m->bface_xyz[9 * (size_t)j + 3 * sl + k] = P(slot[3 * (size_t)b + sl])[k];
+      m->bface_owner[j] = bface_tf[b] >> 2;
+      for (int k = 0; k < 3; ++k) {
+        const float x0 = P(slot[3 * (size_t)b])[k], x1 = P(slot[3 * (size_t)b + 1])[k],
+                    x2 = P(slot[3 * (size_t)b + 2])[k];
+        flo[3 * (size_t)j + k] = std::min(x0, std::min(x1, x2));
+        fhi[3 * (size_t)j + k] = std::max(x0, std::max(x1, x2));
+      }
+    }
+    if (flags & TCT_MESH_RSTAR) {
+      RstarTree tree;
+      rstar_build(flo.data(), fhi.data(), nb, 1e-4f * ext + 1e-30f, tree);
+      m->rstar_nodes = std::move(tree.nodes);
+      m->rstar_list = std::move(tree.faces);
+      m->rstar_height = tree.height;
+      m->has_rstar = true;
+    }
   }
   m->nbvh = (int)nodes.size();
   if (m->host_only) {
@@ -408,6 +433,10 @@ tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32
   if ((st = upload(tetxyz, &m->d_tetxyz, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(tetnbr, &m->d_tetnbr, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(nodes, &m->d_bvh, &m->device_bytes)) != TCT_OK) return fail(st);
+  if (m->has_rstar) {
+    if ((st = upload(m->rstar_nodes, &m->d_rstar, &m->device_bytes)) != TCT_OK) return fail(st);
+    if ((st = upload(m->rstar_list, &m->d_rstar_faces, &m->device_bytes)) != TCT_OK) return fail(st);
+  }
   if ((st = upload(m->perm, &m->d_perm, &m->device_bytes)) != TCT_OK) return fail(st);
   if ((st = upload(m->inv_perm, &m->d_inv_perm, &m->device_bytes)) != TCT_OK) return fail(st);
   std::vector<unsigned long long> zeros(kNumCounters, 0ull);
@@ -423,6 +452,8 @@ void mesh_free_device(tct_mesh* m) {
   if (m->d_tetxyz) (void)hipFree(m->d_tetxyz);
   if (m->d_tetnbr) (void)hipFree(m->d_tetnbr);
   if (m->d_bvh) (void)hipFree(m->d_bvh);
+  if (m->d_rstar) (void)hipFree(m->d_rstar);
+  if (m->d_rstar_faces) (void)hipFree(m->d_rstar_faces);
   if (m->d_perm) (void)hipFree(m->d_perm);
   if (m->d_inv_perm) (void)hipFree(m->d_inv_perm);
   if (m->d_counters) (void)hipFree(m->d_counters);
@@ -431,6 +462,8 @@ void mesh_free_device(tct_mesh* m) {
   m->d_tetxyz = nullptr;
   m->d_tetnbr = nullptr;
   m->d_bvh = nullptr;
+  m->d_rstar = nullptr;
+  m->d_rstar_faces = nullptr;
   m->d_perm = m->d_inv_perm = nullptr;
   m->d_counters = nullptr;
 }

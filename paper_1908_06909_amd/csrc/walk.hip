@@ -259,14 +259,18 @@ __device__ __forceinline__ bool line_hits_box(const Ray& r, float3 inv, const Bv
   return tmin <= tmax;
 }
 
-// Entry search (Section II-E): depth-first over the boundary BVH with skip
-// links (no stack); the convex hull is entered through exactly one face, so
-// the first face passing the exact entry test is the answer.
+// Entry search (Section II-E): depth-first over the boundary BVH (or the
+// R*-tree, kRstar) with skip links (no stack); the convex hull is entered
+// through exactly one face, so the first face passing the exact entry test
+// is the answer.  BVH leaves hold a contiguous range of faces
+// (first * 8 + count); R*-tree leaves index a face list (first * 16 + count).
+template <bool kRstar = false>
 __device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
   float3 inv = make_float3(1.0f / r.d.x, 1.0f / r.d.y, 1.0f / r.d.z);
+  const BvhNode* tree = kRstar ? M.rstar : M.bvh;
   int node = 0;
   while (node >= 0) {
-    const float4* np = reinterpret_cast<const float4*>(M.bvh + node);
+    const float4* np = reinterpret_cast<const float4*>(tree + node);
     float4 n0 = np[0], n1 = np[1];
     BvhNode nd;
     nd.lo[0] = n0.x;
@@ -279,9 +283,17 @@ __device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
     nd.leaf = __float_as_int(n1.w);
     if (line_hits_box(r, inv, nd)) {
       if (nd.leaf >= 0) {
-        int first = nd.leaf >> 3, cnt = nd.leaf & 7;
-        for (int i = 0; i < cnt; ++i)
-          if (enters_face(M, r, first + i, st)) return first + i;
+        if constexpr (kRstar) {
+          const int first = nd.leaf >> 4, cnt = nd.leaf & 15;
+          for (int i = 0; i < cnt; ++i) {
+            const int f = M.rstar_faces[first + i];
+            if (enters_face(M, r, f, st)) return f;
+          }
+        } else {
+          const int first = nd.leaf >> 3, cnt = nd.leaf & 7;
+          for (int i = 0; i < cnt; ++i)
+            if (enters_face(M, r, first + i, st)) return first + i;
+        }
         node = nd.skip;
       } else {
         node = node + 1;
@@ -564,6 +576,7 @@ struct BlockIO {
 
 // Walk the rays of pixel block `block` (of angles [a0, a0 + na_chunk)).
 //   kModeEntry:      out_i32[rid] = entry face (or -1)
+//   kModeEntryRstar: the same, searched through the R*-tree
 //   kModeForward:    out_f32[rid] = sum_i a_ij x_i
 //   kModeBackAtomic: xhat[i] += a_ij y_j through the block's LDS table
 //   kModeBackDirect: xhat[i] += a_ij y_j, one global atomic per segment
@@ -632,8 +645,12 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       q = pixel_src(G, a, i, j);
     else
       q = RegSrc{r.S, r.P, r.U, r.V};
-    int e = (io.entry && MODE != kModeEntry) ? io.entry[rid] : find_entry(M, r, st);
-    if constexpr (MODE == kModeEntry) {
+    int e;
+    if constexpr (MODE == kModeEntryRstar)
+      e = find_entry<true>(M, r, st);
+    else
+      e = (io.entry && MODE != kModeEntry) ? io.entry[rid] : find_entry(M, r, st);
+    if constexpr (MODE == kModeEntry || MODE == kModeEntryRstar) {
       io.out_i32[rid] = e;
     } else if constexpr (MODE == kModeForward) {
       WalkOut<MODE> o;
@@ -825,6 +842,9 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
   switch (mode) {
     case kModeEntry:
       TCT_LAUNCH(kModeEntry);
+      break;
+    case kModeEntryRstar:
+      TCT_LAUNCH(kModeEntryRstar);
       break;
     case kModeForward:
       TCT_LAUNCH(kModeForward);

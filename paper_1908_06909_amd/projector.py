@@ -44,12 +44,14 @@ def _ptr(t: torch.Tensor, dtype, device_index: int, numel: Optional[int] = None,
 class TetMesh:
     """A validated, reordered tetrahedral mesh resident on one device."""
 
-    def __init__(self, verts, tets, nbrs=None, device=None, reorder: bool = True, host_only: bool = False):
+    def __init__(self, verts, tets, nbrs=None, device=None, reorder: bool = True, host_only: bool = False,
+                 rstar: bool = False):
         self.verts = np.ascontiguousarray(verts, dtype=np.float32).reshape(-1, 3)
         self.tets = np.ascontiguousarray(tets, dtype=np.int32).reshape(-1, 4)
         nb = None if nbrs is None else np.ascontiguousarray(nbrs, dtype=np.int32).reshape(-1, 4)
         self.device_index = 0 if host_only else _dev_index(device)
-        flags = (0 if reorder else _lib.TCT_MESH_NO_REORDER) | (_lib.TCT_MESH_HOST_ONLY if host_only else 0)
+        flags = ((0 if reorder else _lib.TCT_MESH_NO_REORDER) | (_lib.TCT_MESH_HOST_ONLY if host_only else 0)
+                 | (_lib.TCT_MESH_RSTAR if rstar else 0))
         h = C.c_void_p()
         call("tct_mesh_create", self.verts.ctypes.data, len(self.verts), self.tets.ctypes.data, len(self.tets),
              None if nb is None else nb.ctypes.data, flags, self.device_index, C.byref(h))
@@ -69,6 +71,26 @@ class TetMesh:
     @property
     def device(self):
         return torch.device("cuda", self.device_index)
+
+    def boundary(self):
+        """Boundary faces in entry-id order: vertices [nb][3][3] (outward
+        orientation) and the user id of each face's tetrahedron."""
+        xyz = np.zeros((self.nboundary, 3, 3), np.float32)
+        owner = np.zeros(self.nboundary, np.int32)
+        call("tct_mesh_boundary", self._h, xyz.ctypes.data, owner.ctypes.data)
+        return xyz, owner
+
+    def rstar(self) -> dict:
+        """The R*-tree (mesh created with rstar=True) in its preorder layout:
+        boxes [n][6], skip and leaf fields [n][2], leaf face list, height."""
+        n, nl, h = C.c_int32(), C.c_int32(), C.c_int32()
+        call("tct_mesh_rstar", self._h, C.byref(n), C.byref(nl), C.byref(h), None, None, None)
+        box = np.zeros((n.value, 6), np.float32)
+        link = np.zeros((n.value, 2), np.int32)
+        lst = np.zeros(nl.value, np.int32)
+        call("tct_mesh_rstar", self._h, C.byref(n), C.byref(nl), C.byref(h), box.ctypes.data, link.ctypes.data,
+             lst.ctypes.data)
+        return {"box": box, "link": link, "list": lst, "height": h.value}
 
     def neighbors(self) -> np.ndarray:
         out = np.zeros((self.nt, 4), np.int32)
@@ -236,10 +258,14 @@ class Projector:
              _stream(self.device))
         return out
 
-    def compute_entry(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def compute_entry(self, out: Optional[torch.Tensor] = None, method: str = "bvh") -> torch.Tensor:
+        """Entry face of every ray (-1: miss) through the boundary BVH or, with
+        method="rstar", the R*-tree (mesh built with rstar=True)."""
+        if method not in ("bvh", "rstar"):
+            raise ValueError(f"unknown entry search {method!r}")
         if out is None:
             out = torch.empty(self.geom.nrays, dtype=torch.int32, device=self.device)
-        call("tct_entry", self.mesh.handle, self.geom.handle,
+        call("tct_entry" if method == "bvh" else "tct_entry_rstar", self.mesh.handle, self.geom.handle,
              _ptr(out, torch.int32, self.mesh.device_index, self.geom.nrays, "entry"), _stream(self.device))
         return out
 
