@@ -199,7 +199,9 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
 #define TCT_BP_ATOMIC_DIRECT 2 /* one float32 atomic add to xhat per segment, as in the paper */
 #define TCT_BP_SHADOW 3        /* deterministic, element-driven: each tetrahedron enumerates the pixels of
                                   its detector shadow per angle, keeps the rays that cross it (the walk's
-                                  exact predicate) and sums length x y_j in ray order in float64 */
+                                  exact predicate) and sums length x y_j in float64 in a fixed order
+                                  (ray order, except elements with exact ties: per angle, then a fixed
+                                  tree over angles) */
 
 /* Backprojection xhat_i = sum_j a_ij y_j (Eq. 3 with the detector index on y).
  *   proj  device float [na][nv][nu]

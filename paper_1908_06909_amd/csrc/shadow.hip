@@ -7,9 +7,10 @@
 // every angle, enumerates the detector pixels inside the tetrahedron's
 // central projection (its "shadow"), decides exactly whether each pixel's ray
 // crosses it, and if so adds the chord length times y_j.  Every element is
-// written once by one lane, so the result needs no atomics and is bitwise
-// reproducible: the sum runs over rays in increasing ray id (angle, row,
-// column) in float64.
+// written once, so the result needs no atomics and is bitwise reproducible:
+// the sum runs in float64 over rays in increasing ray id (angle, row, column),
+// except for the few elements the exact pass takes over, which it sums per
+// angle in a fixed order across one wavefront.
 //
 // Crossing test.  With sigma(p, q) the exact sign of det[P - S, p - S, q - S]
 // for the ray translated by eps U + eps^2 V (the same perturbed predicate the
@@ -30,7 +31,7 @@
 // pixel point; values inside the bound are recomputed in float64 in 3-D, and a
 // tetrahedron where that is still uncertain (a tie at a vertex or an edge) is
 // handed whole to the exact pass, which resolves the six signs with the exact
-// expansion and the perturbation.  Both passes sum in the same ray order.
+// expansion and the perturbation.
 //
 // Chord length.  From the exit and entry faces, L = |d| (t_x - t_e) with
 // t_f = ((a_f - S) . n_f) / (d . n_f) for face f through vertex a_f with
@@ -429,8 +430,15 @@ __global__ __launch_bounds__(kShadowThreads) void shadow_exact_kernel(ShadowArgs
   const int nt = A.M.nt;
   const int count = *A.dirty_count;
   ShadowStats st;
-  for (int k = blockIdx.x * kShadowThreads + threadIdx.x; k < count; k += gridDim.x * kShadowThreads) {
-    const int item = A.dirty[k];
+  // One wavefront per deferred item; lane l takes the angles a_begin + l,
+  // a_begin + l + 64, ... in order, and the 64 partial sums are combined in
+  // a fixed butterfly order (lane 0's result is stored), so the sum is the
+  // same on every run.
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kShadowThreads + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kShadowThreads) >> 6;
+  for (int k = wave; k < count; k += nwaves) {
+    const int item = __builtin_amdgcn_readfirstlane(A.dirty[k]);
     const int chunk = item / nt, t = item - chunk * nt;
     const int a_begin = A.a0 + chunk * A.chunk_len;
     const int a_end = min(A.a0 + A.na, a_begin + A.chunk_len);
@@ -440,7 +448,7 @@ __global__ __launch_bounds__(kShadowThreads) void shadow_exact_kernel(ShadowArgs
     for (int q = 0; q < 4; ++q) v[q] = tet_vertex(tq, q);
     double acc = 0.0;
 #pragma unroll 1
-    for (int a = a_begin; a < a_end; ++a) {
+    for (int a = a_begin + lane; a < a_end; a += 64) {
       FrameD F = load_frame(A.G.frame, a);
       double al[4], be[4];
 #pragma unroll
@@ -513,7 +521,9 @@ __global__ __launch_bounds__(kShadowThreads) void shadow_exact_kernel(ShadowArgs
         }
       }
     }
-    store_result(A, chunk, t, acc);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) store_result(A, chunk, t, acc);
   }
   flush_shadow_stats(A.M, st);
 }
@@ -623,7 +633,8 @@ tct_status backproject_shadow(const tct_mesh* m, const tct_geom* g, const float*
     hipLaunchKernelGGL(shadow_fast_kernel<false>, grid, block, 0, s, A);
   // The exact pass reads the deferred count on the device: a fixed grid
   // strides over however many items the fast pass left.
-  unsigned xgrid = (unsigned)std::min<int64_t>(1024, (int64_t)(items + kShadowThreads - 1) / kShadowThreads);
+  const int64_t waves_per_block = kShadowThreads / 64;
+  unsigned xgrid = (unsigned)std::min<int64_t>(1024, (int64_t)(items + waves_per_block - 1) / waves_per_block);
   if (lds)
     hipLaunchKernelGGL(shadow_exact_kernel<true>, dim3(xgrid), block, 0, s, A);
   else

@@ -80,6 +80,11 @@ def case(name):
             x = synth.uniform_random(len(tets), 8)
             cone = synth.Cone(4.0, 8.0, 48, 40, 2.0 / 40, 2.0 / 40, 0.003, -0.002)
             w = synth.Workload("delaunay3000", verts, tets, x, cone, synth.angles_for(6))
+        elif name == "ties":
+            # Unjittered Kuhn 4^3 with pixel centres on projected vertices and
+            # edges (odd detector, central ray through the origin, angles in
+            # steps of 45 degrees): exact ties for the element-driven pass.
+            w = synth.plain_kuhn(4, 3, 33, 33, 8, pitch=2.0 ** -4)
         elif name == "ragged":
             w = synth.jittered_kuhn(5, 7, 8, 37, 29, 5)
             w.cone = synth.Cone(4.0, 8.0, 37, 29, 0.08, 0.09, 0.013, -0.021)  # wider than the mesh shadow
@@ -217,6 +222,42 @@ def test_cfg0_shadow_is_deterministic_and_accumulates():
     assert np.allclose(acc, a + np.float32(0.25), rtol=0, atol=1e-6)
     g = c.P.backproject(yt, mode="gather").cpu().numpy()
     assert np.allclose(a, g, rtol=1e-5, atol=1e-5)
+
+
+def test_ties_sequences_and_forward():
+    """The walk on rays through vertices and along edges of a regular mesh:
+    the perturbed predicate must pick the oracle's tetrahedra on every ray."""
+    c = case("ties")
+    ids = np.arange(c.orc.nrays)
+    compare_traces(c.P.trace(ids), c.orc.trace(ids), ray_lengths(c, ids))
+    x = c.w.x
+    got = c.P.forward(c.x_internal(x)).cpu().numpy().ravel()
+    assert_within(got, c.orc.forward(x), forward_tolerance(c, x), "ties forward")
+    st = check_stats(c.mesh)
+    assert st["perturbed_ties"] > 0
+
+
+def test_shadow_exact_pass_on_ties():
+    """Rays through mesh vertices and along edges: the element-driven pass
+    hands those elements to its exact pass, which must agree with the oracle
+    and give the same bits on every run."""
+    c = case("ties")
+    rng = np.random.default_rng(35)
+    y = rng.uniform(-1, 1, c.orc.nrays).astype(f32)
+    ref = c.orc.backproject(y)
+    yt = torch.as_tensor(y, device=DEV)
+    c.mesh.stats(reset=True)
+    a = c.P.backproject(yt, mode="shadow")
+    st = check_stats(c.mesh)
+    print(f"ties: {st['fp64_stage']} exact-pass sign evaluations, {st['exact_stage']} exact, "
+          f"{st['perturbed_ties']} perturbed")
+    assert st["fp64_stage"] > 0 and st["perturbed_ties"] > 0
+    b = c.P.backproject(yt, mode="shadow")
+    assert torch.equal(a, b)
+    got = c.to_user(a).astype(np.float64)
+    assert_within(got, ref, _bp_tolerance(c, y), "ties shadow backprojection")
+    g = c.to_user(c.P.backproject(yt, mode="gather")).astype(np.float64)
+    assert_within(g, ref, _bp_tolerance(c, y), "ties gather backprojection")
 
 
 def test_cfg0_adjoint():
