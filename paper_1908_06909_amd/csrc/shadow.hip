@@ -217,6 +217,11 @@ __device__ __forceinline__ void store_result(const ShadowArgs& A, int chunk, int
 // edge values are those listed in entry_face.
 constexpr int kEdgeP[6] = {0, 0, 0, 1, 1, 2};
 constexpr int kEdgeQ[6] = {1, 2, 3, 2, 3, 3};
+// The two faces containing edge e (those opposite its other two vertices)
+// and the edge's sign in the first one's outward edge values.
+constexpr int kEdgeFaceA[6] = {2, 1, 1, 0, 0, 0};
+constexpr int kEdgeFaceB[6] = {3, 3, 2, 3, 2, 1};
+constexpr float kEdgeSignA[6] = {1.f, -1.f, 1.f, 1.f, -1.f, 1.f};
 
 // Largest (smallest) outward edge value of each face: the face is the entry
 // (exit) face of the ray iff this is negative (positive).
@@ -317,6 +322,34 @@ __global__ __launch_bounds__(kShadowThreads, 4) void shadow_fast_kernel(ShadowAr
         n1.y = ((double)pa.x - F.Sx) * n0.x + ((double)pa.y - F.Sy) * n0.y + ((double)pa.z - F.Sz) * n1.x;
         s_plane[f][1][lane] = n1;
       }
+      // Row spans.  The shadow is bounded by the silhouette edges: those
+      // between a face the rays enter by (its outward edge values are all
+      // negative inside it, so their constant sum S_f is negative) and one
+      // they leave by.  For a silhouette edge with outward sign s in its
+      // entry face the whole shadow has s E_e <= 0, so a pixel with
+      // s E_e > bound is no hit; in a row that bounds kx from one side:
+      // kx <= t or kx >= t with t = (s bound - R_e) / cA_e.  With a face seen
+      // nearly edge-on (|S_f| <= bound) the silhouette is uncertain and the
+      // whole box is scanned; near-horizontal edges (|cA_e| < bound / 1024)
+      // are not used.  Skipping pixels never changes a decision: every
+      // scanned pixel is still classified as above.
+      const float Sf[4] = {cC[3] + cC[5] - cC[4], cC[2] - cC[5] - cC[1], cC[0] + cC[4] - cC[2],
+                           cC[1] - cC[3] - cC[0]};
+      const bool spans = fminf(fminf(fabsf(Sf[0]), fabsf(Sf[1])), fminf(fabsf(Sf[2]), fabsf(Sf[3]))) > bound;
+      float rA[6], sb[6];
+      bool upper[6], lower[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        const bool fa = Sf[kEdgeFaceA[e]] < 0.f, fb = Sf[kEdgeFaceB[e]] < 0.f;
+        const float sgn = fa ? kEdgeSignA[e] : -kEdgeSignA[e];
+        const float g = sgn * cA[e];
+        const bool use = spans && fa != fb && fabsf(cA[e]) * 1024.0f >= bound;
+        upper[e] = use && g > 0.f;
+        lower[e] = use && g < 0.f;
+        rA[e] = use ? 1.0f / cA[e] : 0.f;
+        sb[e] = sgn * bound;
+      }
+      const float box_hi = (float)(i1 - i0);
       const float* yrow = A.proj + (size_t)a * nv * nu;
 #pragma unroll 1
       for (int j = j0; j <= j1 && !deferred; ++j) {
@@ -326,8 +359,19 @@ __global__ __launch_bounds__(kShadowThreads, 4) void shadow_fast_kernel(ShadowAr
         float R[6];
 #pragma unroll
         for (int e = 0; e < 6; ++e) R[e] = fmaf(y, cB[e], cC[e]);
+        float lo = 0.f, hi = box_hi;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          const float t = (sb[e] - R[e]) * rA[e];
+          hi = upper[e] ? fminf(hi, t) : hi;
+          lo = lower[e] ? fmaxf(lo, t) : lo;
+        }
+        // Slack for the rounding of t (relative) and of the comparison.
+        hi = fmaxf(hi + fmaf(fabsf(hi), 0x1p-22f, 0x1p-10f), -1.0f);
+        lo = fminf(lo - fmaf(fabsf(lo), 0x1p-22f, 0x1p-10f), box_hi + 1.0f);
+        const int ilo = i0 + max(0, (int)ceilf(lo)), ihi = i0 + min(i1 - i0, (int)floorf(hi));
 #pragma unroll 1
-        for (int i = i0; i <= i1; ++i) {
+        for (int i = ilo; i <= ihi; ++i) {
           // Issued first so that their latency overlaps the classification.
           const float yv = yr[i];
           const float uu = ut[i];
