@@ -50,10 +50,9 @@ constexpr float kFilterAbs = 7.888609052210118e-31f;  // 2^-100
 struct Ray {
   float3 S, P, U, V;
   float3 d;    // d_hi = fl(P - S)
-  float3 dlo;  // P - S - d_hi (exact)
   float3 ad;   // |d_hi|
-  float3 M;    // M_hi, M_lo: the ray point at t = 1/2 as an unevaluated sum
-  float3 Mlo;
+  double dx64, dy64, dz64;  // P - S (exact in float64)
+  double Mx64, My64, Mz64;  // the ray point at t = 1/2
   float dn;    // |d| (Euclidean)
   float dd;    // |d|^2
   float dinf;  // max |d_i|
@@ -71,21 +70,19 @@ struct LaneStats {
   __device__ __forceinline__ void add_failed() { failed++; }
 };
 
-// The ray is carried with an exact direction d = d_hi + d_lo and an almost
-// exact point M = M_hi + M_lo at t = 1/2 (error O(u^2 |M|)), so positions on
-// it near the mesh can be formed to a relative accuracy set by their distance
-// to the mesh features rather than by the distance to the source.
+// The ray is carried with d_hi = fl(P - S) for the float32 filters and, in
+// float64, with the exact direction P - S and the point M at t = 1/2 (one
+// float64 rounding), so positions on it near the mesh can be formed to a
+// relative accuracy set by their distance to the mesh features rather than
+// by the distance to the source.
 __device__ __forceinline__ void finish_ray(Ray& r, float mesh_extent) {
-  float e;
-  two_sum_f(r.P.x, -r.S.x, r.d.x, r.dlo.x);
-  two_sum_f(r.P.y, -r.S.y, r.d.y, r.dlo.y);
-  two_sum_f(r.P.z, -r.S.z, r.d.z, r.dlo.z);
-  two_sum_f(r.S.x, 0.5f * r.d.x, r.M.x, e);
-  r.Mlo.x = e + 0.5f * r.dlo.x;
-  two_sum_f(r.S.y, 0.5f * r.d.y, r.M.y, e);
-  r.Mlo.y = e + 0.5f * r.dlo.y;
-  two_sum_f(r.S.z, 0.5f * r.d.z, r.M.z, e);
-  r.Mlo.z = e + 0.5f * r.dlo.z;
+  r.d = f3sub(r.P, r.S);
+  r.dx64 = (double)r.P.x - r.S.x;
+  r.dy64 = (double)r.P.y - r.S.y;
+  r.dz64 = (double)r.P.z - r.S.z;
+  r.Mx64 = r.S.x + 0.5 * r.dx64;
+  r.My64 = r.S.y + 0.5 * r.dy64;
+  r.Mz64 = r.S.z + 0.5 * r.dz64;
   r.ad = f3abs(r.d);
   r.dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
   r.dn = sqrtf(r.dd);
@@ -155,21 +152,15 @@ __device__ __noinline__ double crossing_s_fp64(float3 S, float3 P, float3 on, fl
 // parameter for the element sizes met in practice.
 constexpr float kGrazingCos2 = 1.0f / 4096.0f;
 
-// D = v - Q for the ray point Q = M + s d, formed from the exact pairs:
-// s d_hi = p + pe exactly (fused multiply-add residual), v - M_hi = t1 + t1e
-// exactly (two-sum), and the small terms pe + s d_lo + M_lo summed apart, so
-// that |D - (v - Q)| <= 3.1 u |D| + 28 u^2 R componentwise.
+// D = v - Q for the ray point Q = M + s d, in float64: M, v - M and the
+// fused s d term each carry one float64 rounding of the source-distance
+// scale R, so with the final rounding to float32
+// |D - (v - Q)| <= u |D| + 2^-51 R componentwise, inside the allowance
+// 3.1 u |D| + 28 u^2 R the walk filter below is built on.
 __device__ __forceinline__ float3 offset_from_ray(const Ray& r, float s, float3 v) {
-  float3 p = make_float3(s * r.d.x, s * r.d.y, s * r.d.z);
-  float3 pe = make_float3(fmaf(s, r.d.x, -p.x), fmaf(s, r.d.y, -p.y), fmaf(s, r.d.z, -p.z));
-  float3 rho = make_float3((pe.x + s * r.dlo.x) + r.Mlo.x, (pe.y + s * r.dlo.y) + r.Mlo.y,
-                           (pe.z + s * r.dlo.z) + r.Mlo.z);
-  float3 t1, t1e;
-  two_sum_f(v.x, -r.M.x, t1.x, t1e.x);
-  two_sum_f(v.y, -r.M.y, t1.y, t1e.y);
-  two_sum_f(v.z, -r.M.z, t1.z, t1e.z);
-  return make_float3((t1.x - p.x) + (t1e.x - rho.x), (t1.y - p.y) + (t1e.y - rho.y),
-                     (t1.z - p.z) + (t1e.z - rho.z));
+  const double sd = (double)s;
+  return make_float3((float)fma(-sd, r.dx64, (double)v.x - r.Mx64), (float)fma(-sd, r.dy64, (double)v.y - r.My64),
+                     (float)fma(-sd, r.dz64, (double)v.z - r.Mz64));
 }
 
 // Walk filter.  With w = fl(d_hi x D) and e = fl(a - v), the exact edge value
@@ -205,6 +196,13 @@ __device__ __forceinline__ int fast_sign(float3 e, float3 w, float3 W) {
   float B = kFilterRel * (fabsf(e.x) * W.x + fabsf(e.y) * W.y + fabsf(e.z) * W.z) + kFilterAbs;
   return E > B ? 1 : (E < -B ? -1 : 2);
 }
+
+// The ray leaves through the face (v, a_{k+1}, a_{k+2}) opposite entry slot
+// k (indices mod 3) for which E(v, a_{k+1}) < 0 < E(v, a_{k+2}), the first of
+// k = 2, 0, 1 that qualifies.  When the three signs are certain (nonzero)
+// this is a table on n = neg0 | neg1 << 1 | neg2 << 2, two bits per entry;
+// 3 = none (all three signs equal: the walk has failed).
+constexpr unsigned kExitFace = 0xD90Bu;
 
 __device__ __forceinline__ int walk_sign(float3 e, float3 w, float K) {
   float E = e.x * w.x + e.y * w.y + e.z * w.z;
@@ -329,21 +327,25 @@ constexpr int kLdsProbes = 8;
 constexpr int kLdsWindow = 64;
 
 __device__ __forceinline__ void lds_accumulate(int* keys, float* vals, int tet, float v, float* xhat) {
-  unsigned h = ((unsigned)tet * 2654435761u) >> kLdsHashShift;
+  unsigned slot = ((unsigned)tet * 2654435761u) >> kLdsHashShift;
+  int k = atomicCAS(keys + slot, -1, tet);
+  if (k != -1 && k != tet) {
 #pragma unroll 1
-  for (int p = 0; p < kLdsProbes; ++p) {
-    unsigned slot = (h + p) & (kLdsSlots - 1);
-    int k = atomicCAS(keys + slot, -1, tet);
-    if (k == -1 || k == tet) {
-      // The table pointer arrives as a generic pointer; cast it back to the
-      // LDS address space so the add is a native ds_add_f32 (through a
-      // generic pointer it becomes a flat atomic or a compare-and-swap loop).
-      __hip_atomic_fetch_add((__attribute__((address_space(3))) float*)(vals + slot), v, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int p = 1; p < kLdsProbes; ++p) {
+      slot = (slot + 1) & (kLdsSlots - 1);
+      k = atomicCAS(keys + slot, -1, tet);
+      if (k == -1 || k == tet) break;
+    }
+    if (k != -1 && k != tet) {
+      unsafeAtomicAdd(xhat + tet, v);
       return;
     }
   }
-  unsafeAtomicAdd(xhat + tet, v);
+  // The table pointer arrives as a generic pointer; cast it back to the
+  // LDS address space so the add is a native ds_add_f32 (through a
+  // generic pointer it becomes a flat atomic or a compare-and-swap loop).
+  __hip_atomic_fetch_add((__attribute__((address_space(3))) float*)(vals + slot), v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int MODE>
@@ -392,8 +394,8 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, cons
   w.a2 = make_float3(q2.x, q2.y, q2.z);
   w.v = make_float3(q3.x, q3.y, q3.z);
   // Ray parameters are kept as s = t - 1/2 around the reference point M.  Each
-  // step forms D = v - Q for the current entry point Q = M + s_in d from the
-  // exact pairs (offset_from_ray), so both the exit-face signs and the
+  // step forms D = v - Q for the current entry point Q = M + s_in d in
+  // float64 (offset_from_ray), so both the exit-face signs and the
   // crossing are evaluated from a vector of element size whose error is a
   // few ulps of itself, not of the source distance.  Only segment lengths
   // are accumulated, never differences of rounded parameters.
@@ -420,30 +422,30 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   float3 wv = f3cross(r.d, D);
   float K = r.dinf * (kWalkRel * fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))) + r.kR);
   float3 e0 = f3sub(w.a0, v), e1 = f3sub(w.a1, v), e2 = f3sub(w.a2, v);
-  int s0 = walk_sign(e0, wv, K);
-  int s1 = walk_sign(e1, wv, K);
-  int s2 = walk_sign(e2, wv, K);
-  if (s0 == 2) s0 = resolve_src(q, v, w.a0, st);
-  if (s1 == 2) s1 = resolve_src(q, v, w.a1, st);
-  if (s2 == 2) s2 = resolve_src(q, v, w.a2, st);
+  const float E0 = f3dot(e0, wv), E1 = f3dot(e1, wv), E2 = f3dot(e2, wv);
+  const float m0 = fabsf(E0) - fmaf(fabsf(e0.x) + fabsf(e0.y) + fabsf(e0.z), K, kFilterAbs);
+  const float m1 = fabsf(E1) - fmaf(fabsf(e1.x) + fabsf(e1.y) + fabsf(e1.z), K, kFilterAbs);
+  const float m2 = fabsf(E2) - fmaf(fabsf(e2.x) + fabsf(e2.y) + fabsf(e2.z), K, kFilterAbs);
   int k;
-  float3 ei, ej;
-  if (s0 < 0 && s1 > 0) {
-    k = 2;
-    ei = e0;
-    ej = e1;
-  } else if (s1 < 0 && s2 > 0) {
-    k = 0;
-    ei = e1;
-    ej = e2;
-  } else if (s2 < 0 && s0 > 0) {
-    k = 1;
-    ei = e2;
-    ej = e0;
+  if (fminf(m0, fminf(m1, m2)) > 0.f) {
+    const unsigned n = (__float_as_uint(E0) >> 31) | ((__float_as_uint(E1) >> 31) << 1) |
+                       ((__float_as_uint(E2) >> 31) << 2);
+    k = (int)((kExitFace >> (2 * n)) & 3u);
   } else {
+    const int s0 = m0 > 0.f ? (E0 > 0.f ? 1 : -1) : resolve_src(q, v, w.a0, st);
+    const int s1 = m1 > 0.f ? (E1 > 0.f ? 1 : -1) : resolve_src(q, v, w.a1, st);
+    const int s2 = m2 > 0.f ? (E2 > 0.f ? 1 : -1) : resolve_src(q, v, w.a2, st);
+    k = (s0 < 0 && s1 > 0) ? 2 : (s1 < 0 && s2 > 0) ? 0 : (s2 < 0 && s0 > 0) ? 1 : 3;
+  }
+  if (k == 3) {
     st.add_failed();
     return false;
   }
+  const bool k0 = k == 0, k2 = k == 2;
+  const float3 ei = make_float3(k2 ? e0.x : (k0 ? e1.x : e2.x), k2 ? e0.y : (k0 ? e1.y : e2.y),
+                                k2 ? e0.z : (k0 ? e1.z : e2.z));
+  const float3 ej = make_float3(k2 ? e1.x : (k0 ? e2.x : e0.x), k2 ? e1.y : (k0 ? e2.y : e0.y),
+                                k2 ? e1.z : (k0 ? e2.z : e0.z));
   float3 n = f3cross(ei, ej);
   float den = f3dot(r.d, n);
   float dt;
@@ -451,7 +453,6 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     dt = f3dot(D, n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
   } else {
     st.add_grazing();
-    const bool k0 = k == 0, k2 = k == 2;
     const float3 ai = make_float3(k2 ? w.a0.x : (k0 ? w.a1.x : w.a2.x), k2 ? w.a0.y : (k0 ? w.a1.y : w.a2.y),
                                   k2 ? w.a0.z : (k0 ? w.a1.z : w.a2.z));
     const float3 aj = make_float3(k2 ? w.a1.x : (k0 ? w.a2.x : w.a0.x), k2 ? w.a1.y : (k0 ? w.a2.y : w.a0.y),
@@ -683,7 +684,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
 // ---------------------------------------------------------------- kernels
 
 template <int MODE>
-__global__ __launch_bounds__(256, MODE == kModeBackAtomic ? 4 : 1) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
+__global__ __launch_bounds__(256, 4) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
                                                          BlockIO io) {
   if constexpr (MODE == kModeBackAtomic) {
     __shared__ int tkeys[kLdsSlots];
