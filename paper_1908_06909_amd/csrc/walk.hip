@@ -320,15 +320,28 @@ __device__ __forceinline__ unsigned remap_local(unsigned p, unsigned f, unsigned
 // table is flushed after each window: it only holds the tetrahedra one
 // window of the bundle touches.  A segment that finds no slot within
 // kLdsProbes probes goes straight to global memory.
+//
+// The table sums in 64-bit fixed point: LDS integer atomics run several
+// times faster than float ones on this chip.  Each term t = L y_j |d| is
+// rounded to a multiple of 2^-54 M, M >= 2^(e-1) the block's largest |y_j| |d|
+// (2^e the next power of two), and at most 256 terms (one per ray of the
+// block) meet in a slot per window, so the integer sum cannot overflow and
+// is exact; the flush converts it back to float.  Every term keeps an
+// absolute error below 2^-54 2^e, far below a float32 rounding of the
+// terms that matter.
 constexpr int kLdsSlots = 4096;
 constexpr int kLdsHashShift = 20;  // multiplicative hash keeps the top 12 bits
 static_assert(kLdsSlots == (1 << (32 - kLdsHashShift)), "hash width must match the table size");
 constexpr int kLdsProbes = 8;
 constexpr int kLdsWindow = 64;
 
-__device__ __forceinline__ void lds_accumulate(int* keys, float* vals, int tet, float v, float* xhat) {
+__device__ __forceinline__ void lds_accumulate(int* keys, long long* vals, int tet, float v, float scale,
+                                               float* xhat) {
   unsigned slot = ((unsigned)tet * 2654435761u) >> kLdsHashShift;
-  int k = atomicCAS(keys + slot, -1, tet);
+  // Most segments find their tetrahedron already placed by a neighbouring
+  // ray of the bundle: a plain read settles those without an atomic.
+  int k = keys[slot];
+  if (k != tet) k = atomicCAS(keys + slot, -1, tet);
   if (k != -1 && k != tet) {
 #pragma unroll 1
     for (int p = 1; p < kLdsProbes; ++p) {
@@ -342,10 +355,10 @@ __device__ __forceinline__ void lds_accumulate(int* keys, float* vals, int tet, 
     }
   }
   // The table pointer arrives as a generic pointer; cast it back to the
-  // LDS address space so the add is a native ds_add_f32 (through a
-  // generic pointer it becomes a flat atomic or a compare-and-swap loop).
-  __hip_atomic_fetch_add((__attribute__((address_space(3))) float*)(vals + slot), v, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_WORKGROUP);
+  // LDS address space so the add is a native ds_add_u64 (through a generic
+  // pointer it becomes a flat atomic).
+  __hip_atomic_fetch_add((__attribute__((address_space(3))) long long*)(vals + slot), __float2ll_rn(v * scale),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int MODE>
@@ -357,7 +370,8 @@ struct WalkOut {
   float weight = 0.f;
   float* xhat = nullptr;
   int* lds_keys = nullptr;  // per-block accumulation table (BWD), null = direct atomics
-  float* lds_vals = nullptr;
+  long long* lds_vals = nullptr;
+  float lds_scale = 1.f;  // fixed-point scale of the table (a power of two)
   // TRACE / GATHER_FILL output cursor
   int32_t* out_tet = nullptr;
   float* out_len = nullptr;
@@ -469,7 +483,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   if constexpr (MODE == kModeForward) {
     o.acc += (double)dt * (double)w.xcur;
   } else if constexpr (MODE == kModeBackAtomic) {
-    if (dt > 0.f) lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.xhat);
+    if (dt > 0.f) lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.lds_scale, o.xhat);
   } else if constexpr (MODE == kModeBackDirect) {
     if (dt > 0.f) unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
   } else if constexpr (MODE == kModeCountAll) {
@@ -586,16 +600,17 @@ struct BlockIO {
 // Every thread of the block must call it (the backprojection synchronises).
 template <int MODE, bool kLeanSrc = false>
 __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G, const TileMap& tm, int64_t block,
-                                           int a0, int na_chunk, const BlockIO& io, int* tkeys, float* tvals) {
+                                           int a0, int na_chunk, const BlockIO& io, int* tkeys,
+                                           long long* tvals) {
   int a, i, j;
   bool active = tile_ray(G, tm, block, threadIdx.x, a0, na_chunk, &a, &i, &j);
   LaneStats st;
   if constexpr (MODE == kModeBackAtomic) {
+    __shared__ float s_wmax[4];
     for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
       tkeys[k] = -1;
-      tvals[k] = 0.f;
+      tvals[k] = 0;
     }
-    __syncthreads();
     Ray r;
     PixelSrc q{};
     WalkOut<MODE> o;
@@ -615,6 +630,17 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
         alive = true;
       }
     }
+    // Fixed-point scale from the block's largest ray weight.
+    float aw = alive ? fabsf(o.weight) : 0.f;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) aw = fmaxf(aw, __shfl_xor(aw, off, 64));
+    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = aw;
+    __syncthreads();
+    const float maxw = fmaxf(fmaxf(s_wmax[0], s_wmax[1]), fmaxf(s_wmax[2], s_wmax[3]));
+    int ex = 0;
+    (void)frexpf(maxw, &ex);
+    o.lds_scale = ldexpf(1.0f, min(54 - ex, 120));
+    const double inv_scale = 1.0 / (double)o.lds_scale;
     // The block's rays advance together in windows of kLdsWindow steps;
     // after each window the table is added to xhat and cleared, so it only
     // ever holds the tetrahedra of one window of the ray bundle.
@@ -625,9 +651,9 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
         const int key = tkeys[k];
         if (key >= 0) {
-          unsafeAtomicAdd(io.out_f32 + key, tvals[k]);
+          unsafeAtomicAdd(io.out_f32 + key, (float)((double)tvals[k] * inv_scale));
           tkeys[k] = -1;
-          tvals[k] = 0.f;
+          tvals[k] = 0;
         }
       }
       __syncthreads();
@@ -688,7 +714,7 @@ __global__ __launch_bounds__(256, 4) void pixel_walk_kernel(MeshView M, GeomView
                                                          BlockIO io) {
   if constexpr (MODE == kModeBackAtomic) {
     __shared__ int tkeys[kLdsSlots];
-    __shared__ float tvals[kLdsSlots];
+    __shared__ long long tvals[kLdsSlots];
     walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, tkeys, tvals);
   } else {
     walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, nullptr, nullptr);
@@ -743,7 +769,7 @@ __global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __r
     io.lds_table = d.lds_table;
     if constexpr (MODE == kModeBackAtomic) {
       __shared__ int tkeys[kLdsSlots];
-      __shared__ float tvals[kLdsSlots];
+      __shared__ long long tvals[kLdsSlots];
       walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
     } else {
       walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
