@@ -16,7 +16,11 @@ namespace tct {
 // One bounding-volume-hierarchy node over boundary faces, 32 bytes, stored
 // in depth-first preorder: an interior node's first child is the next node;
 // `skip` is the node after its whole subtree (-1 past the end).  `leaf` is
-// -1 for interior nodes, else first_face * 8 + count (count <= 7).
+// -1 for interior nodes, else first_face * 8 + count (count <= 7).  The
+// boundary BVH starts with a header (node 0, skip = number of groups) and
+// one record per group of faces with a common outward-normal axis (nodes
+// 1..ng: normal bounds in lo/hi, skip = the node after the group's tree,
+// leaf = the group's root node); the group trees follow.
 struct BvhNode {
   float lo[3];
   int skip;

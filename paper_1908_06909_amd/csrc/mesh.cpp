@@ -324,7 +324,68 @@ tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32
         it.c[k] = (it.lo[k] + it.hi[k]) * 0.5f;
       }
     }
-    bvh_build(items, 0, nb, 1e-4f * ext + 1e-30f, nodes, order);
+    // Faces are grouped by the dominant axis of their outward normal (+x, -x,
+    // +y, -y, +z, -z), one BVH per group under a common root.  A ray enters
+    // only through a face it meets from outside (d . n < 0), so the search
+    // skips every group whose normals all face away from it: for a convex
+    // mesh that is about half of the boundary, the side the ray leaves by.
+    std::vector<int> grp(nb);
+    std::vector<double> nrm(3 * (size_t)nb);
+    for (int b = 0; b < nb; ++b) {
+      const float* p0 = P(slot[3 * (size_t)b]);
+      const float* p1 = P(slot[3 * (size_t)b + 1]);
+      const float* p2 = P(slot[3 * (size_t)b + 2]);
+      double e1[3], e2[3];
+      for (int k = 0; k < 3; ++k) {
+        e1[k] = (double)p1[k] - p0[k];
+        e2[k] = (double)p2[k] - p0[k];
+      }
+      double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+      const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      int ax = 0;
+      for (int k = 0; k < 3; ++k) {
+        n[k] /= len;
+        nrm[3 * (size_t)b + k] = n[k];
+        if (std::fabs(n[k]) > std::fabs(n[ax])) ax = k;
+      }
+      grp[b] = 2 * ax + (n[ax] < 0 ? 1 : 0);
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const BuildItem& a, const BuildItem& b) { return grp[a.id] < grp[b.id]; });
+    const float pad = 1e-4f * ext + 1e-30f;
+    std::vector<std::pair<int, int>> ranges;
+    for (int begin = 0, g = 0; g < 6; ++g) {
+      int end = begin;
+      while (end < nb && grp[items[end].id] == g) ++end;
+      if (end > begin) ranges.push_back({begin, end});
+      begin = end;
+    }
+    // Node 0 is a header (skip = number of groups), nodes 1..ng the group
+    // records (normal bounds in lo/hi, skip = the node after the group's
+    // tree, leaf = the group's root node); the trees follow.
+    const int ng = (int)ranges.size();
+    nodes.resize(1 + ng);
+    nodes[0] = BvhNode();
+    nodes[0].skip = ng;
+    nodes[0].leaf = -1;
+    for (int gi = 0; gi < ng; ++gi) {
+      double lo[3] = {1, 1, 1}, hi[3] = {-1, -1, -1};
+      for (int i = ranges[gi].first; i < ranges[gi].second; ++i)
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], nrm[3 * (size_t)items[i].id + k]);
+          hi[k] = std::max(hi[k], nrm[3 * (size_t)items[i].id + k]);
+        }
+      const int root = (int)nodes.size();
+      bvh_build(items, ranges[gi].first, ranges[gi].second, pad, nodes, order);
+      BvhNode& rec = nodes[1 + gi];
+      // Normal bounds, widened by 1e-6 against the float rounding of the box.
+      for (int k = 0; k < 3; ++k) {
+        rec.lo[k] = (float)lo[k] - 1e-6f;
+        rec.hi[k] = (float)hi[k] + 1e-6f;
+      }
+      rec.skip = (int)nodes.size();
+      rec.leaf = root;
+    }
     for (auto& nd : nodes)
       if (nd.skip >= (int)nodes.size()) nd.skip = -1;
     // Boundary faces in entry-id order, and the R*-tree over them when asked.

@@ -257,17 +257,15 @@ __device__ __forceinline__ bool line_hits_box(const Ray& r, float3 inv, const Bv
   return tmin <= tmax;
 }
 
-// Entry search (Section II-E): depth-first over the boundary BVH (or the
-// R*-tree, kRstar) with skip links (no stack); the convex hull is entered
+// Depth-first scan of a preorder tree with skip links (no stack) from
+// `node` until `end` (-1: the end of the array): the convex hull is entered
 // through exactly one face, so the first face passing the exact entry test
 // is the answer.  BVH leaves hold a contiguous range of faces
 // (first * 8 + count); R*-tree leaves index a face list (first * 16 + count).
-template <bool kRstar = false>
-__device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
-  float3 inv = make_float3(1.0f / r.d.x, 1.0f / r.d.y, 1.0f / r.d.z);
-  const BvhNode* tree = kRstar ? M.rstar : M.bvh;
-  int node = 0;
-  while (node >= 0) {
+template <bool kRstar>
+__device__ int scan_tree(const MeshView& M, const BvhNode* tree, const Ray& r, float3 inv, int node, int end,
+                         LaneStats& st) {
+  while (node >= 0 && node != end) {
     const float4* np = reinterpret_cast<const float4*>(tree + node);
     float4 n0 = np[0], n1 = np[1];
     BvhNode nd;
@@ -301,6 +299,33 @@ __device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
     }
   }
   return -1;
+}
+
+// Entry search (Section II-E) through the boundary BVH, or the R*-tree
+// (kRstar).  The BVH is split into groups of faces by the axis of their
+// outward normal; a ray enters only through a face with d . n < 0, so a
+// group is skipped when the smallest d . n over its normals' bounding box is
+// positive (beyond the rounding of that bound: products of |n| <= 1 with d,
+// three of them summed, err below 3u |d|_1; the margin is 1e-6 |d|_1).
+template <bool kRstar = false>
+__device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
+  float3 inv = make_float3(1.0f / r.d.x, 1.0f / r.d.y, 1.0f / r.d.z);
+  if constexpr (kRstar) {
+    return scan_tree<true>(M, M.rstar, r, inv, 0, -1, st);
+  } else {
+    const float4* h = reinterpret_cast<const float4*>(M.bvh);
+    const float l1 = fabsf(r.d.x) + fabsf(r.d.y) + fabsf(r.d.z);
+    const int ng = __float_as_int(h[0].w);
+    for (int g = 1; g <= ng; ++g) {
+      const float4 lo = h[2 * g], hi = h[2 * g + 1];  // normal bounds; lo.w = end node, hi.w = root node
+      const float m = fminf(r.d.x * lo.x, r.d.x * hi.x) + fminf(r.d.y * lo.y, r.d.y * hi.y) +
+                      fminf(r.d.z * lo.z, r.d.z * hi.z);
+      if (m > 1e-6f * l1) continue;
+      const int f = scan_tree<false>(M, M.bvh, r, inv, __float_as_int(hi.w), __float_as_int(lo.w), st);
+      if (f >= 0) return f;
+    }
+    return -1;
+  }
 }
 
 __device__ __forceinline__ unsigned remap_local(unsigned p, unsigned f, unsigned back) {
