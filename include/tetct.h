@@ -193,8 +193,9 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
                        tct_stream s);
 
 #define TCT_BP_ATOMIC 0        /* ray-driven float32 scatter (Section II-F); each 16x16-pixel block first sums
-                                  its segments per tetrahedron in on-chip memory, then adds one atomic per
-                                  distinct tetrahedron to xhat */
+                                  its segments per tetrahedron in on-chip memory (64-bit fixed point scaled to
+                                  the block's largest |y_j| |P_j - S|: every term is kept to 2^-54 of it),
+                                  then adds one float atomic per distinct tetrahedron to xhat */
 #define TCT_BP_GATHER 1        /* deterministic: per-tetrahedron lists of (ray, length), summed in ray order */
 #define TCT_BP_ATOMIC_DIRECT 2 /* one float32 atomic add to xhat per segment, as in the paper */
 #define TCT_BP_SHADOW 3        /* deterministic, element-driven: each tetrahedron enumerates the pixels of

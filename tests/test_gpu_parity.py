@@ -196,6 +196,20 @@ def test_cfg0_backproject(mode):
     check_stats(c.mesh)
 
 
+@pytest.mark.parametrize("mode", ["atomic", "shadow", "gather"])
+def test_cfg0_backproject_wide_dynamic_range(mode):
+    """Projection values spanning eight decades with both signs, so a pixel
+    block mixes terms 10^8 apart: the scatter's fixed-point block table keeps
+    every term to 2^-54 of the block's largest, which stays inside the bar."""
+    c = case("cfg0")
+    rng = np.random.default_rng(36)
+    y = (rng.choice([-1.0, 1.0], c.orc.nrays) * 10.0 ** rng.uniform(-4, 4, c.orc.nrays)).astype(f32)
+    ref = c.orc.backproject(y)
+    got = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode)).astype(np.float64)
+    assert_within(got, ref, _bp_tolerance(c, y), f"cfg0 wide-range backprojection {mode}")
+    check_stats(c.mesh)
+
+
 def test_cfg0_gather_is_deterministic_and_accumulates():
     c = case("cfg0")
     rng = np.random.default_rng(32)
