@@ -8,9 +8,12 @@ cached for the step) + forward projection A x + atomic backprojection
 A^T b of that projection.  The value is tet-segments (walk steps, zero-length
 passages included) per second over both walks.
 
-Prints one JSON line.  Options: --steps K (timed), --warmup W, --gpus N (1
-only), --no-cpu-baseline, --gather (also time the deterministic gather
-backprojection), --json-extra FILE (write per-kernel details).
+Prints one JSON line.  Options: --steps K (timed, default 5; kernel times
+are medians over the steps), --warmup W (default 2), --gpus N (1 only),
+--no-cpu-baseline, --gather (also time the deterministic gather
+backprojection), --json-extra FILE (write per-kernel details).  The roofline
+object gives the dominant kernel's algorithmic bandwidth against the 8 TB/s
+peak and against this box's measured copy bandwidth (`stream_gbs`).
 """
 
 from __future__ import annotations
@@ -66,8 +69,8 @@ BWD_BYTES_PER_SEG = 28  # walk geometry (20) + read-modify-write of xhat_i (8)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=1, help="workload index (1 = the benchmark configuration)")
     ap.add_argument("--angles", type=int, default=0,
                     help="use only the first N angles of the workload (profiling passes); 0 = all")
@@ -437,7 +440,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = mesh.stats(reset=True)
-    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    ms = {k: float(np.median([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
     # Segments per walk: the counters hold forward + backprojection walks of
     # every timed step (the entry pass walks nothing).
     segs_total = st["segments"]
@@ -511,6 +514,24 @@ def main():
                                                 "hbm_frac": BWD_BYTES_PER_SEG * segs_per_walk / (t_ms * 1e-3)
                                                 / 1e9 / HBM_PEAK_GBS}
     mesh.stats(reset=True)
+    # The box's own streaming bandwidth (device-to-device copy of 1 GiB: one
+    # read and one write per byte), for the roofline against what the memory
+    # delivers in practice.
+    n_copy = 1 << 28
+    src = torch.ones(n_copy, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    stream_gbs = 5 * 2 * 4 * n_copy / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+    out["roofline"]["stream_gbs"] = stream_gbs
+    out["roofline"]["frac_of_stream"] = ach / stream_gbs
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     if args.json_extra:
