@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--init-sweep", default="",
                     help="comma-separated mesh sizes (see --init-mesh): entry search (BVH and R*-tree) vs walk "
                          "time, one 1024x1024 projection each")
-    ap.add_argument("--bp", default="atomic", choices=["atomic", "shadow", "atomic_direct", "gather"],
+    ap.add_argument("--bp", default="atomic", choices=["atomic", "fixed", "shadow", "atomic_direct", "gather"],
                     help="backprojection of the timed step")
     ap.add_argument("--json-extra", default=None)
     ap.add_argument("--batch-cgls", type=int, default=0, metavar="NPROB",
@@ -449,15 +449,17 @@ def main():
     fwd_gbs = FWD_BYTES_PER_SEG * segs_per_walk / (ms["forward"] * 1e-3) / 1e9
     bwd_gbs = BWD_BYTES_PER_SEG * segs_per_walk / (ms["backproject"] * 1e-3) / 1e9
     bp_kernel = {"atomic": "atomic backprojection walk (pixel_walk_kernel<2>)",
-                 "atomic_direct": "direct-atomic backprojection walk (pixel_walk_kernel<2>)",
+                 "atomic_direct": "direct-atomic backprojection walk (pixel_walk_kernel<7>)",
                  "gather": "gather backprojection (walk fill + sort + segment sum)",
-                 "shadow": "element-driven backprojection (shadow_backproject_kernel)"}[args.bp]
+                 "fixed": "reproducible fixed-point scatter (pixel_walk_kernel<9>)",
+                 "shadow": "element-driven backprojection (shadow_fast_kernel + shadow_exact_kernel)"}[args.bp]
     if ms["forward"] >= ms["backproject"]:
         dom, ach, bps, dom_ms, key = "forward walk (pixel_walk_kernel<1>)", fwd_gbs, FWD_BYTES_PER_SEG, ms["forward"], \
             "pixel_walk_kernel<1>"
     else:
         dom, ach, bps, dom_ms = bp_kernel, bwd_gbs, BWD_BYTES_PER_SEG, ms["backproject"]
-        key = {"atomic": "pixel_walk_kernel<2>", "atomic_direct": "pixel_walk_kernel<7>"}.get(args.bp, "")
+        key = {"atomic": "pixel_walk_kernel<2>", "atomic_direct": "pixel_walk_kernel<7>",
+               "fixed": "pixel_walk_kernel<9>"}.get(args.bp, "")
     traffic_bytes = measured_traffic_bytes(key) if (key and args.workload == 1 and not args.angles) else None
     traffic = traffic_bytes / (dom_ms * 1e-3) / 1e9 if traffic_bytes else None
     out = {
@@ -498,7 +500,7 @@ def main():
         "ingest_s": ingest_s,
     }
     # The other backprojection variants, one timed call each (not part of the step).
-    others = [m for m in ("atomic", "shadow", "atomic_direct") if m != args.bp]
+    others = [m for m in ("atomic", "fixed", "shadow", "atomic_direct") if m != args.bp]
     if args.gather and args.bp != "gather":
         others.append("gather")
     for mode in others:

@@ -198,6 +198,12 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
                                   then adds one float atomic per distinct tetrahedron to xhat */
 #define TCT_BP_GATHER 1        /* deterministic: per-tetrahedron lists of (ray, length), summed in ray order */
 #define TCT_BP_ATOMIC_DIRECT 2 /* one float32 atomic add to xhat per segment, as in the paper */
+#define TCT_BP_FIXED 4         /* reproducible ray-driven scatter: the atomic walk with every term rounded to
+                                  a multiple of 2^-s, one s per launch (terms stay below 2^(62 - ceil(log2
+                                  rays)) in magnitude), so all sums are exact integers and the result is the
+                                  same bits on every run; terms far below the launch's largest |y_j| |P_j - S|
+                                  lose relative precision (quantum 2^-(62 - ceil(log2 rays)) times the
+                                  power of two above it) */
 #define TCT_BP_SHADOW 3        /* deterministic, element-driven: each tetrahedron enumerates the pixels of
                                   its detector shadow per angle, keeps the rays that cross it (the walk's
                                   exact predicate) and sums length x y_j in float64 in a fixed order

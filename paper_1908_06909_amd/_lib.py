@@ -33,6 +33,7 @@ TCT_BP_ATOMIC = 0
 TCT_BP_GATHER = 1
 TCT_BP_ATOMIC_DIRECT = 2
 TCT_BP_SHADOW = 3
+TCT_BP_FIXED = 4
 TCT_DOT_WORKSPACE = 512
 TCT_VECSET_DOT_WORKSPACE = 256
 

@@ -321,6 +321,8 @@ tct_status tct_backproject_range(const tct_mesh* m, const tct_geom* g, const flo
   if (mode == TCT_BP_GATHER)
     return backproject_gather(m, g, proj, xhat, accumulate, entry, r->tile_u, r->a0, r->na, (hipStream_t)s);
   if (mode == TCT_BP_SHADOW) return backproject_shadow(m, g, proj, xhat, accumulate, r->a0, r->na, (hipStream_t)s);
+  if (mode == TCT_BP_FIXED)
+    return backproject_fixed(m, g, proj, xhat, accumulate, entry, r->tile_u, r->a0, r->na, (hipStream_t)s);
   if (mode != TCT_BP_ATOMIC && mode != TCT_BP_ATOMIC_DIRECT) {
     set_error("tct_backproject_range: unknown mode");
     return TCT_E_ARG;
@@ -358,6 +360,8 @@ tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* pr
   if (mode == TCT_BP_GATHER)
     return backproject_gather(m, g, proj, xhat, accumulate, entry, default_tile_u(), 0, g->na, (hipStream_t)s);
   if (mode == TCT_BP_SHADOW) return backproject_shadow(m, g, proj, xhat, accumulate, 0, g->na, (hipStream_t)s);
+  if (mode == TCT_BP_FIXED)
+    return backproject_fixed(m, g, proj, xhat, accumulate, entry, default_tile_u(), 0, g->na, (hipStream_t)s);
   if (mode != TCT_BP_ATOMIC && mode != TCT_BP_ATOMIC_DIRECT) {
     set_error("tct_backproject: unknown mode");
     return TCT_E_ARG;

@@ -15,12 +15,14 @@ enum WalkMode {
   kModeGatherFill = 6,
   kModeBackDirect = 7,  // backprojection with one global atomic per segment
   kModeEntryRstar = 8,  // entry search through the R*-tree
+  kModeBackFixed = 9,   // backprojection through the block table into 64-bit fixed-point sums (reproducible)
 };
 
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
                              const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
                              int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
-                             hipStream_t s, int lds_table = 0);
+                             hipStream_t s, int lds_table = 0, unsigned long long* acc64 = nullptr,
+                             const int* scale_exp = nullptr);
 
 tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
                               const int32_t* entry, int tile_u, int lds_table, hipStream_t s);
@@ -31,6 +33,9 @@ tct_status launch_list_walk(int mode, const tct_mesh* m, const tct_geom* g, cons
 
 tct_status launch_fill(float* p, int64_t n, float v, hipStream_t s);
 tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s);
+
+tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
+                             const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s);
 
 tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
                               const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s);

@@ -361,7 +361,7 @@ constexpr int kLdsProbes = 8;
 constexpr int kLdsWindow = 64;
 
 __device__ __forceinline__ void lds_accumulate(int* keys, long long* vals, int tet, float v, float scale,
-                                               float* xhat) {
+                                               float* xhat, unsigned long long* acc64) {
   unsigned slot = ((unsigned)tet * 2654435761u) >> kLdsHashShift;
   // Most segments find their tetrahedron already placed by a neighbouring
   // ray of the bundle: a plain read settles those without an atomic.
@@ -375,7 +375,10 @@ __device__ __forceinline__ void lds_accumulate(int* keys, long long* vals, int t
       if (k == -1 || k == tet) break;
     }
     if (k != -1 && k != tet) {
-      unsafeAtomicAdd(xhat + tet, v);
+      if (acc64)
+        atomicAdd(acc64 + tet, (unsigned long long)__float2ll_rn(v * scale));
+      else
+        unsafeAtomicAdd(xhat + tet, v);
       return;
     }
   }
@@ -397,6 +400,7 @@ struct WalkOut {
   int* lds_keys = nullptr;  // per-block accumulation table (BWD), null = direct atomics
   long long* lds_vals = nullptr;
   float lds_scale = 1.f;  // fixed-point scale of the table (a power of two)
+  unsigned long long* acc64 = nullptr;  // fixed-point result (reproducible mode), else null
   // TRACE / GATHER_FILL output cursor
   int32_t* out_tet = nullptr;
   float* out_len = nullptr;
@@ -507,8 +511,8 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   float4 rec = M.faces[4 * (size_t)tet + f];
   if constexpr (MODE == kModeForward) {
     o.acc += (double)dt * (double)w.xcur;
-  } else if constexpr (MODE == kModeBackAtomic) {
-    if (dt > 0.f) lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.lds_scale, o.xhat);
+  } else if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed) {
+    if (dt > 0.f) lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.lds_scale, o.xhat, o.acc64);
   } else if constexpr (MODE == kModeBackDirect) {
     if (dt > 0.f) unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
   } else if constexpr (MODE == kModeCountAll) {
@@ -612,6 +616,8 @@ struct BlockIO {
   int32_t* keys;
   float* vals;
   int lds_table;
+  unsigned long long* acc64;  // kModeBackFixed: fixed-point sums [nt]
+  const int* scale_exp;       // kModeBackFixed: log2 of their scale
 };
 
 // Walk the rays of pixel block `block` (of angles [a0, a0 + na_chunk)).
@@ -619,6 +625,7 @@ struct BlockIO {
 //   kModeEntryRstar: the same, searched through the R*-tree
 //   kModeForward:    out_f32[rid] = sum_i a_ij x_i
 //   kModeBackAtomic: xhat[i] += a_ij y_j through the block's LDS table
+//   kModeBackFixed:  acc64[i] += a_ij y_j 2^scale_exp, exact integer sums
 //   kModeBackDirect: xhat[i] += a_ij y_j, one global atomic per segment
 //   kModeCountPos:   counts[rid - rid0] = positive-length visits
 //   kModeGatherFill: keys/vals at offsets[rid - rid0]
@@ -630,7 +637,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
   int a, i, j;
   bool active = tile_ray(G, tm, block, threadIdx.x, a0, na_chunk, &a, &i, &j);
   LaneStats st;
-  if constexpr (MODE == kModeBackAtomic) {
+  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed) {
     __shared__ float s_wmax[4];
     for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
       tkeys[k] = -1;
@@ -665,6 +672,12 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     int ex = 0;
     (void)frexpf(maxw, &ex);
     o.lds_scale = ldexpf(1.0f, min(54 - ex, 120));
+    if constexpr (MODE == kModeBackFixed) {
+      // One scale for the whole launch, so that every sum is an exact
+      // integer whatever the order of the additions.
+      o.lds_scale = ldexpf(1.0f, *io.scale_exp);
+      o.acc64 = io.acc64;
+    }
     const double inv_scale = 1.0 / (double)o.lds_scale;
     // The block's rays advance together in windows of kLdsWindow steps;
     // after each window the table is added to xhat and cleared, so it only
@@ -676,7 +689,10 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
         const int key = tkeys[k];
         if (key >= 0) {
-          unsafeAtomicAdd(io.out_f32 + key, (float)((double)tvals[k] * inv_scale));
+          if constexpr (MODE == kModeBackFixed)
+            atomicAdd(io.acc64 + key, (unsigned long long)tvals[k]);
+          else
+            unsafeAtomicAdd(io.out_f32 + key, (float)((double)tvals[k] * inv_scale));
           tkeys[k] = -1;
           tvals[k] = 0;
         }
@@ -737,7 +753,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
 template <int MODE>
 __global__ __launch_bounds__(256, 4) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
                                                          BlockIO io) {
-  if constexpr (MODE == kModeBackAtomic) {
+  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed) {
     __shared__ int tkeys[kLdsSlots];
     __shared__ long long tvals[kLdsSlots];
     walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, tkeys, tvals);
@@ -848,6 +864,38 @@ __global__ __launch_bounds__(256) void list_walk_kernel(MeshView M, GeomView G, 
   flush_stats(M, st, active ? 1 : 0);
 }
 
+// Reproducible scatter: the largest |y_j| of the launch (as float bits,
+// which order like the values for non-negative floats), the scale exponent
+// derived from it, the zeroed integer sums and their conversion at the end.
+__global__ void max_abs_kernel(const float* y, int64_t n, unsigned* out) {
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(y[i]));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void fixed_scale_kernel(const unsigned* max_bits, float max_dlen, int K, int* exp_out) {
+  const float w = __uint_as_float(*max_bits) * max_dlen;
+  int e = 0;
+  if (w > 0.f && w < INFINITY) (void)frexpf(w, &e);
+  *exp_out = min(max(K - e, -120), 120);
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+__global__ void fixed_finish_kernel(const unsigned long long* acc, const int* scale_exp, float* xhat, int n,
+                                    int accumulate) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = ldexp((double)(long long)acc[i], -*scale_exp);
+  xhat[i] = accumulate ? (float)((double)xhat[i] + v) : (float)v;
+}
+
 __global__ void fill_f32_kernel(float* p, int64_t n, float v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -877,7 +925,7 @@ static TileMap make_tiles(const GeomView& g, int tile_u) {
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
                              const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
                              int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
-                             hipStream_t s, int lds_table) {
+                             hipStream_t s, int lds_table, unsigned long long* acc64, const int* scale_exp) {
   MeshView M = m->view();
   GeomView G = g->view();
   TileMap tm = make_tiles(G, tile_u);
@@ -887,7 +935,7 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
     set_error("too many rays in one launch");
     return TCT_E_ARG;
   }
-  BlockIO io{entry, in, out_f32, out_i32, counts, offsets, keys, vals, lds_table};
+  BlockIO io{entry, in, out_f32, out_i32, counts, offsets, keys, vals, lds_table, acc64, scale_exp};
   dim3 grid((unsigned)blocks), block(256);
 #define TCT_LAUNCH(MODE_) \
   hipLaunchKernelGGL(pixel_walk_kernel<MODE_>, grid, block, 0, s, M, G, tm, a0, na_chunk, io)
@@ -906,6 +954,9 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
         TCT_LAUNCH(kModeBackAtomic);
       else
         TCT_LAUNCH(kModeBackDirect);
+      break;
+    case kModeBackFixed:
+      TCT_LAUNCH(kModeBackFixed);
       break;
     case kModeCountPos:
       TCT_LAUNCH(kModeCountPos);
@@ -955,6 +1006,66 @@ tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float*
   }
   return launch_pixel_walk(kModeBackAtomic, m, g, 0, g->na, entry, proj, xhat, nullptr, nullptr, nullptr, nullptr,
                            nullptr, tile_u, s, lds_table);
+}
+
+// Reproducible scatter (TCT_BP_FIXED).  Every term L y_j |d_j| is rounded
+// to a multiple of 2^-scale_exp, one scale for the launch: 2^e bounds the
+// largest |y_j| |d_j| (|d_j| <= the longest pixel ray of the angle range)
+// and K = 62 - ceil(log2(rays)), so each term is below 2^K in magnitude and
+// no tetrahedron's sum of at most `rays` terms can reach 2^62.  The block
+// tables and the global sums then add integers, exactly, in any order.
+tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
+                             const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s) {
+  if (m->nt <= 0) return TCT_OK;
+  const int64_t per_angle = (int64_t)g->cone.nu * g->cone.nv;
+  const int64_t nrays = per_angle * a_count;
+  if (nrays <= 0) return accumulate ? TCT_OK : launch_fill(xhat, m->nt, 0.f, s);
+  // Longest pixel ray |P - S| over the angle range: the distance is convex
+  // in the pixel position, so a detector corner attains it.
+  double dmax = 0.0;
+  const float us[2] = {g->ut.front(), g->ut.back()}, vs[2] = {g->vt.front(), g->vt.back()};
+  for (int a = a_begin; a < a_begin + a_count; ++a) {
+    const float* f = &g->frame[12 * (size_t)a];
+    for (float u : us)
+      for (float v : vs) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double c = (double)f[3 + k] + (double)u * f[6 + k] + (double)v * f[9 + k] - f[k];
+          d2 += c * c;
+        }
+        dmax = std::max(dmax, std::sqrt(d2));
+      }
+  }
+  int bits = 1;
+  while (bits < 62 && ((int64_t)1 << bits) < nrays) ++bits;
+  const int K = 62 - bits;
+  // Scratch: [max |y| bits, scale exponent, pad][nt int64 sums].
+  unsigned long long* acc = nullptr;
+  char* scratch = nullptr;
+  TCT_HIP(hipMallocAsync((void**)&scratch, 256 + 8 * (size_t)m->nt, s));
+  unsigned* max_bits = (unsigned*)scratch;
+  int* scale_exp = (int*)(scratch + 4);
+  acc = (unsigned long long*)(scratch + 256);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, (unsigned long long*)scratch, (int64_t)1);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((m->nt + 255) / 256)), dim3(256), 0, s, acc, (int64_t)m->nt);
+  const float* y = proj + per_angle * a_begin;
+  const unsigned mgrid = (unsigned)std::min<int64_t>(4096, (nrays + 255) / 256);
+  hipLaunchKernelGGL(max_abs_kernel, dim3(mgrid), dim3(256), 0, s, y, nrays, max_bits);
+  hipLaunchKernelGGL(fixed_scale_kernel, dim3(1), dim3(1), 0, s, (const unsigned*)max_bits,
+                     (float)(dmax * 1.0001), K, scale_exp);
+  hipError_t e = hipGetLastError();
+  tct_status st = TCT_OK;
+  if (e == hipSuccess)
+    st = launch_pixel_walk(kModeBackFixed, m, g, a_begin, a_count, entry, proj, xhat, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, tile_u, s, 1, acc, scale_exp);
+  if (e == hipSuccess && st == TCT_OK) {
+    hipLaunchKernelGGL(fixed_finish_kernel, dim3((unsigned)((m->nt + 255) / 256)), dim3(256), 0, s,
+                       (const unsigned long long*)acc, (const int*)scale_exp, xhat, m->nt, accumulate);
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(scratch, s);
+  if (e != hipSuccess) return hip_fail(e, "reproducible scatter launch");
+  return st;
 }
 
 // ---------------------------------------------------------------- batches

@@ -14,8 +14,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_GATHER, TCT_BP_SHADOW, call, lib, tct_cone,
-                   tct_paper_stats, tct_range, tct_stats)
+from ._lib import (TCT_BP_ATOMIC, TCT_BP_ATOMIC_DIRECT, TCT_BP_FIXED, TCT_BP_GATHER, TCT_BP_SHADOW, call, lib,
+                   tct_cone, tct_paper_stats, tct_range, tct_stats)
 
 
 def _stream(device) -> int:
@@ -205,7 +205,7 @@ class Projector:
     def backproject(self, y: torch.Tensor, mode: str = "atomic", out: Optional[torch.Tensor] = None,
                     accumulate: bool = False, use_cache: bool = True) -> torch.Tensor:
         m = {"atomic": TCT_BP_ATOMIC, "atomic_direct": TCT_BP_ATOMIC_DIRECT, "gather": TCT_BP_GATHER,
-             "shadow": TCT_BP_SHADOW}[mode]
+             "shadow": TCT_BP_SHADOW, "fixed": TCT_BP_FIXED}[mode]
         if out is None:
             out = torch.empty(self.nt, dtype=torch.float32, device=self.device)
             accumulate = False
@@ -231,7 +231,7 @@ class Projector:
         return out, st.as_dict()
 
     _BP_MODES = {"atomic": TCT_BP_ATOMIC, "atomic_direct": TCT_BP_ATOMIC_DIRECT, "gather": TCT_BP_GATHER,
-                 "shadow": TCT_BP_SHADOW}
+                 "shadow": TCT_BP_SHADOW, "fixed": TCT_BP_FIXED}
 
     def forward_range(self, x: torch.Tensor, a0: int, na: int, out: torch.Tensor, tile_u: int = 8,
                       use_cache: bool = True) -> torch.Tensor:

@@ -182,7 +182,7 @@ def _bp_tolerance(c, y):
     return 1e-5 * chord_w + nterm * 2.0 ** -24 * absbp + 1e-30
 
 
-@pytest.mark.parametrize("mode", ["atomic", "atomic_direct", "gather", "shadow"])
+@pytest.mark.parametrize("mode", ["atomic", "atomic_direct", "gather", "shadow", "fixed"])
 def test_cfg0_backproject(mode):
     c = case("cfg0")
     rng = np.random.default_rng(31)
@@ -208,6 +208,49 @@ def test_cfg0_backproject_wide_dynamic_range(mode):
     got = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode)).astype(np.float64)
     assert_within(got, ref, _bp_tolerance(c, y), f"cfg0 wide-range backprojection {mode}")
     check_stats(c.mesh)
+
+
+def _fixed_quantum(c, y):
+    """Upper bound on the reproducible scatter's rounding step: 2^-(K - e)
+    with K = 62 - ceil(log2 rays) and 2^e above max |y_j| |d_j| (one power of
+    two of slack for the float32 product the library forms)."""
+    n = c.orc.nrays
+    bits = max(1, int(np.ceil(np.log2(n))))
+    dmax = float(ray_lengths(c, np.arange(n)).max()) * 1.0001
+    _, e = np.frexp(float(np.abs(y).max()) * dmax)
+    return 2.0 ** -((62 - bits) - int(e) - 1)
+
+
+def test_cfg0_wide_range_fixed_within_its_quantum():
+    """The reproducible scatter rounds every term to one quantum per launch:
+    on projection values spanning eight decades its error per element stays
+    within the oracle bar plus half a quantum per term."""
+    c = case("cfg0")
+    rng = np.random.default_rng(36)
+    y = (rng.choice([-1.0, 1.0], c.orc.nrays) * 10.0 ** rng.uniform(-4, 4, c.orc.nrays)).astype(f32)
+    ref = c.orc.backproject(y)
+    got = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode="fixed")).astype(np.float64)
+    ids = np.arange(c.orc.nrays)
+    nterm = np.zeros(c.orc.nt)
+    for tt, ll in c.orc.trace(ids):
+        np.add.at(nterm, tt[ll > 0], 1)
+    q = _fixed_quantum(c, y)
+    print(f"fixed quantum {q:.3e}")
+    assert_within(got, ref, _bp_tolerance(c, y) + nterm * q * 0.5, "cfg0 wide-range backprojection fixed")
+
+
+def test_cfg0_fixed_is_reproducible_and_accumulates():
+    c = case("cfg0")
+    rng = np.random.default_rng(37)
+    yt = torch.as_tensor(rng.uniform(-1, 1, c.orc.nrays).astype(f32), device=DEV)
+    a = c.P.backproject(yt, mode="fixed").cpu().numpy()
+    b = c.P.backproject(yt, mode="fixed").cpu().numpy()
+    assert np.array_equal(a.view(np.int32), b.view(np.int32))
+    base = torch.full((c.orc.nt,), 0.25, dtype=torch.float32, device=DEV)
+    acc = c.P.backproject(yt, mode="fixed", out=base.clone(), accumulate=True).cpu().numpy()
+    assert np.allclose(acc, a + np.float32(0.25), rtol=0, atol=1e-6)
+    g = c.P.backproject(yt, mode="gather").cpu().numpy()
+    assert np.allclose(a, g, rtol=1e-5, atol=1e-5)
 
 
 def test_cfg0_gather_is_deterministic_and_accumulates():
@@ -423,6 +466,29 @@ def test_ragged_detector_and_missing_rays():
         bp = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode))
         assert np.linalg.norm(bp - ref_bp) <= 1e-5 * np.linalg.norm(ref_bp), mode
     assert_within(bp.astype(np.float64), ref_bp, _bp_tolerance(c, y), "ragged shadow backprojection")
+    check_stats(c.mesh)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_full_size_fixed_reproducible_adjoint_and_atomic_agreement(name):
+    """Full-size reproducible scatter in the launch the benchmark's
+    backprojection uses: the same bits twice, the adjoint identity against
+    the forward projection, and agreement with the float scatter."""
+    c = case(name)
+    rng = np.random.default_rng(6)
+    xi = c.x_internal(c.w.x.astype(f32))
+    Ax = c.P.forward(xi).reshape(-1)
+    y = torch.as_tensor(rng.uniform(0, 1, c.geom.nrays).astype(f32), device=DEV)
+    fx = c.P.backproject(y, mode="fixed")
+    fx2 = c.P.backproject(y, mode="fixed")
+    assert torch.equal(fx, fx2)
+    at = c.P.backproject(y, mode="atomic")
+    lhs = float(torch.dot(Ax.double(), y.double()))
+    rhs = float(torch.dot(xi.double(), fx.double()))
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs), (lhs, rhs)
+    err = (fx.double() - at.double()).abs()
+    assert float(err.max()) <= 2e-4 * float(at.double().abs().max()), float(err.max())
+    assert float(err.norm()) <= 2e-5 * float(at.double().norm())
     check_stats(c.mesh)
 
 
