@@ -328,11 +328,6 @@ __device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
   }
 }
 
-__device__ __forceinline__ unsigned remap_local(unsigned p, unsigned f, unsigned back) {
-  unsigned rank = p - (p > f ? 1u : 0u);
-  return rank + (rank >= back ? 1u : 0u);
-}
-
 // Per-block accumulation table for the backprojection.  Neighbouring rays
 // of a pixel block cross mostly the same tetrahedra (at the benchmark pitch a
 // 16 x 16 block spans about two elements), so scattering every segment with a
@@ -410,13 +405,21 @@ struct WalkOut {
   int64_t count = 0;
 };
 
-// Walk state between steps: the entry face as three vertex slots (local
-// indices packed in `loc`), the fourth vertex v (local index `locv`), the
-// current tetrahedron and the ray parameter where the ray entered it.
+// Walk state between steps: the entry face as three vertex slots, the
+// fourth vertex v, the current tetrahedron and the ray parameter where the
+// ray entered it.  `loc` holds the local indices (0..3 within the current
+// tetrahedron) of slots 0, 1, 2 and of v in four 4-bit fields.
+//
+// Crossing face f (the face opposite local vertex f) into a neighbour whose
+// opposite vertex has local index `back` there, the three shared vertices
+// keep their order: local indices are sorted the same way in both elements,
+// so a shared vertex of rank r among the face's vertices has local index
+// r + (r >= back) in the neighbour, with r = p - (p > f).  walk_step applies
+// this to all four fields at once.
 struct WalkState {
   float3 a0, a1, a2, v;
   int tet;
-  unsigned loc, locv;
+  unsigned loc;
   float s_in;
   float xcur;  // forward projection: x of the current tetrahedron
   int steps;
@@ -430,8 +433,7 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, cons
   float4 q0 = bq[0], q1 = bq[1], q2 = bq[2], q3 = bq[3];
   w.tet = __float_as_int(q0.w);
   unsigned lp = (unsigned)__float_as_int(q1.w);
-  w.loc = lp & 63u;          // local index of slot s in bits 2s..2s+1
-  w.locv = (lp >> 6) & 3u;   // local index of v
+  w.loc = (lp & 3u) | ((lp & 12u) << 2) | ((lp & 48u) << 4) | ((lp & 192u) << 6);
   w.a0 = make_float3(q0.x, q0.y, q0.z);
   w.a1 = make_float3(q1.x, q1.y, q1.z);
   w.a2 = make_float3(q2.x, q2.y, q2.z);
@@ -457,9 +459,9 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
                                           WalkOut<MODE>& o, LaneStats& st) {
   if (w.steps > M.nt) {
     st.add_failed();
+    st.steps += w.steps;
     return false;
   }
-  w.steps++;
   const float3 v = w.v;
   float3 D = offset_from_ray(r, w.s_in, v);
   float3 wv = f3cross(r.d, D);
@@ -482,8 +484,10 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   }
   if (k == 3) {
     st.add_failed();
+    st.steps += w.steps;
     return false;
   }
+  w.steps++;
   const bool k0 = k == 0, k2 = k == 2;
   const float3 ei = make_float3(k2 ? e0.x : (k0 ? e1.x : e2.x), k2 ? e0.y : (k0 ? e1.y : e2.y),
                                 k2 ? e0.z : (k0 ? e1.z : e2.z));
@@ -502,15 +506,15 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
                                   k2 ? w.a1.z : (k0 ? w.a2.z : w.a0.z));
     dt = (float)(crossing_s_fp64(q.S(), q.P(), v, ai, aj) - (double)w.s_in);
   }
-  dt = fminf(fmaxf(dt, 0.0f), fmaxf(0.5f - w.s_in, 0.0f));
-  st.steps++;
+  dt = __builtin_amdgcn_fmed3f(dt, 0.0f, fmaxf(0.5f - w.s_in, 0.0f));
   if (dt == 0.f) st.add_zero();
   // Next tetrahedron across the exit face (local face index loc[k]).
   const int tet = w.tet;
-  unsigned f = (w.loc >> (2 * k)) & 3u;
-  float4 rec = M.faces[4 * (size_t)tet + f];
+  const unsigned sh = 4u * (unsigned)k;
+  unsigned f = (w.loc >> sh) & 3u;
+  float4 rec = M.faces[(size_t)(((unsigned)tet << 2) | f)];
   if constexpr (MODE == kModeForward) {
-    o.acc += (double)dt * (double)w.xcur;
+    o.acc = fma((double)dt, (double)w.xcur, o.acc);  // the product is exact
   } else if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed) {
     if (dt > 0.f) lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.lds_scale, o.xhat, o.acc64);
   } else if constexpr (MODE == kModeBackDirect) {
@@ -535,21 +539,24 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   // dependent fetch behind the next step's arithmetic.
   asm volatile("" : "+v"(rec.x), "+v"(rec.y), "+v"(rec.z), "+v"(rec.w));
   int packed = __float_as_int(rec.x);
-  if (packed < 0) return false;
+  if (packed < 0) {
+    st.steps += w.steps;
+    return false;
+  }
   unsigned back = (unsigned)packed & 3u;
-  unsigned nl0 = remap_local((w.loc >> 0) & 3u, f, back);
-  unsigned nl1 = remap_local((w.loc >> 2) & 3u, f, back);
-  unsigned nl2 = remap_local((w.loc >> 4) & 3u, f, back);
-  unsigned nv_ = remap_local(w.locv, f, back);
-  // Slot k takes v (component-wise selects keep the slots in registers).
-  nl0 = k == 0 ? nv_ : nl0;
-  nl1 = k == 1 ? nv_ : nl1;
-  nl2 = k == 2 ? nv_ : nl2;
+  // All four fields at once.  Adding 7 - f to a field sets its bit 3
+  // exactly when p > f, and adding 8 - back to the rank sets it exactly when
+  // r >= back; the fields hold at most 10, so no carry crosses into the next.
+  // (The field of slot k, whose vertex is not on the face, is replaced.)
+  const unsigned L = w.loc;
+  const unsigned R = L - (((L + 0x7777u - f * 0x1111u) >> 3) & 0x1111u);
+  const unsigned N = R + (((R + 0x8888u - back * 0x1111u) >> 3) & 0x1111u);
   w.a0 = make_float3(k == 0 ? v.x : w.a0.x, k == 0 ? v.y : w.a0.y, k == 0 ? v.z : w.a0.z);
   w.a1 = make_float3(k == 1 ? v.x : w.a1.x, k == 1 ? v.y : w.a1.y, k == 1 ? v.z : w.a1.z);
   w.a2 = make_float3(k == 2 ? v.x : w.a2.x, k == 2 ? v.y : w.a2.y, k == 2 ? v.z : w.a2.z);
-  w.loc = nl0 | (nl1 << 2) | (nl2 << 4);
-  w.locv = back;
+  // Slot k takes v's new index; the neighbour's opposite vertex is `back`.
+  const unsigned fieldk = 0xFu << sh;
+  w.loc = (((N & 0xFFFu) & ~fieldk) | ((N >> 12) << sh)) | (back << 12);
   w.v = xyz(rec);
   w.tet = packed >> 2;
   w.s_in += dt;
