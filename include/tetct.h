@@ -185,6 +185,18 @@ tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_s
  * test admits one face per ray. */
 tct_status tct_entry_rstar(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s);
 
+/* The same entry faces found by projecting the boundary instead of searching
+ * a tree (Section II-E defines the entry face; the search structure is this
+ * library's).  For each angle, every boundary face whose plane has the
+ * source on its outer side is projected onto the detector plane in double
+ * precision, and the pixels inside the bounding box of the projection,
+ * widened by a twentieth of the pitch, are tested with the exact entry test
+ * on their float32 rays.  The result is identical to tct_entry's: the exact
+ * test admits one face per ray of a convex mesh.
+ *   entry: device int32 [nrays], every element written (-1 for a miss)
+ * Errors: TCT_E_ARG for a null output or a mesh/geometry device mismatch. */
+tct_status tct_entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s);
+
 /* Forward projection b_j = sum_i a_ij x_i (Eq. 2).
  *   x     device float [nt], internal order
  *   proj  device float [na][nv][nu], overwritten

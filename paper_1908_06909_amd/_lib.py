@@ -87,6 +87,7 @@ _SIGS = {
     "tct_geom_destroy": (None, [_P]),
     "tct_entry": (C.c_int, [_P, _P, _P, _P]),
     "tct_entry_rstar": (C.c_int, [_P, _P, _P, _P]),
+    "tct_entry_raster": (C.c_int, [_P, _P, _P, _P]),
     "tct_forward": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "tct_backproject": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, _P, _P]),
     "tct_trace": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P]),

@@ -280,6 +280,17 @@ tct_status tct_entry_rstar(const tct_mesh* m, const tct_geom* g, int32_t* entry,
                            nullptr, nullptr, default_tile_u(), (hipStream_t)s);
 }
 
+tct_status tct_entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!entry) {
+    set_error("tct_entry_raster: null output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return entry_raster(m, g, entry, (hipStream_t)s);
+}
+
 namespace {
 tct_status check_range(const tct_geom* g, const tct_range* r) {
   if (!r || r->a0 < 0 || r->na < 0 || r->a0 + r->na > g->na) {

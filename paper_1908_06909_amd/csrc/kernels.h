@@ -32,6 +32,7 @@ tct_status launch_list_walk(int mode, const tct_mesh* m, const tct_geom* g, cons
                             const int64_t* offsets, int32_t* tets, float* lens, hipStream_t s);
 
 tct_status launch_fill(float* p, int64_t n, float v, hipStream_t s);
+tct_status entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry, hipStream_t s);
 tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s);
 
 tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,

@@ -769,6 +769,125 @@ __global__ __launch_bounds__(256, 4) void pixel_walk_kernel(MeshView M, GeomView
   }
 }
 
+// Entry faces by projecting the boundary (an alternative to the tree
+// searches that gives the same faces).  For one angle, the rays are the lines
+// from the source S through the pixel points; a boundary face can only be
+// entered by them when S lies on the outer side of its plane.  Such a face is
+// projected centrally onto the detector plane in float64, and the pixels
+// whose abscissa and ordinate fall inside the bounding box of the projection,
+// widened by a twentieth of the pitch, are tested with the exact entry test
+// of the tree searches on their own float32 rays.  The widening covers the
+// rounding of the pixel points (about 1e-4 of the pitch), so every pixel
+// whose ray enters through the face is tested; a convex mesh is entered
+// through exactly one face per ray, so each pixel is written at most once
+// and the result equals the tree searches'.  Faces whose plane nearly
+// contains S, and vertices at or behind S's plane parallel to the detector,
+// fall back to testing the whole detector for that face.
+//
+// A wavefront takes 64 boundary faces of one angle: each lane classifies one
+// face, then the wavefront walks the candidate faces one by one with a lane
+// per pixel of the face's box.  When faces and angles are too few to fill
+// the chip (coarse meshes, single projections), gridDim.z wavefronts share
+// each face's box, taking interleaved runs of 64 pixels.
+constexpr int kRasterWaves = 4;
+
+__device__ __forceinline__ void raster_box(const GeomView& G, const float* f, float3 a0, float3 a1, float3 a2,
+                                           int* i0, int* i1, int* j0, int* j1) {
+  const double Sx = f[0], Sy = f[1], Sz = f[2], Cx = f[3], Cy = f[4], Cz = f[5];
+  const double Ux = f[6], Uy = f[7], Uz = f[8], Vx = f[9], Vy = f[10], Vz = f[11];
+  // Outward normal of the face and the side of its plane S is on.
+  const double e1x = (double)a1.x - a0.x, e1y = (double)a1.y - a0.y, e1z = (double)a1.z - a0.z;
+  const double e2x = (double)a2.x - a0.x, e2y = (double)a2.y - a0.y, e2z = (double)a2.z - a0.z;
+  const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+  const double wx = (double)a0.x - Sx, wy = (double)a0.y - Sy, wz = (double)a0.z - Sz;
+  const double side = wx * nx + wy * ny + wz * nz;
+  const double scale = sqrt((wx * wx + wy * wy + wz * wz) * (nx * nx + ny * ny + nz * nz));
+  *i0 = 0;
+  *i1 = -1;
+  *j0 = 0;
+  *j1 = -1;
+  if (side > 1e-9 * scale) return;  // S on the inner side: no ray enters here
+  const int nu = G.nu, nv = G.nv;
+  bool whole = !(side < -1e-9 * scale);
+  // Detector plane normal and the source's distance to that plane.
+  const double Nx = Uy * Vz - Uz * Vy, Ny = Uz * Vx - Ux * Vz, Nz = Ux * Vy - Uy * Vx;
+  const double cs = (Cx - Sx) * Nx + (Cy - Sy) * Ny + (Cz - Sz) * Nz;
+  const double uu = Ux * Ux + Uy * Uy + Uz * Uz, vv = Vx * Vx + Vy * Vy + Vz * Vz;
+  double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+  const float3 pts[3] = {a0, a1, a2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double px = (double)pts[k].x - Sx, py = (double)pts[k].y - Sy, pz = (double)pts[k].z - Sz;
+    const double den = px * Nx + py * Ny + pz * Nz;
+    if (!(den * cs > 0.0) || !(fabs(den) > 1e-9 * fabs(cs))) whole = true;
+    const double lam = cs / den;
+    const double xx = Sx + lam * px - Cx, xy = Sy + lam * py - Cy, xz = Sz + lam * pz - Cz;
+    const double u = (xx * Ux + xy * Uy + xz * Uz) / uu, v = (xx * Vx + xy * Vy + xz * Vz) / vv;
+    umin = fmin(umin, u);
+    umax = fmax(umax, u);
+    vmin = fmin(vmin, v);
+    vmax = fmax(vmax, v);
+  }
+  if (whole) {
+    *i0 = 0;
+    *i1 = nu - 1;
+    *j0 = 0;
+    *j1 = nv - 1;
+    return;
+  }
+  // Pixel abscissae are affine in the index up to float rounding.
+  const double u0 = G.ut[0], du = nu > 1 ? ((double)G.ut[nu - 1] - u0) / (nu - 1) : 1.0;
+  const double v0 = G.vt[0], dv = nv > 1 ? ((double)G.vt[nv - 1] - v0) / (nv - 1) : 1.0;
+  double ia = (umin - u0) / du, ib = (umax - u0) / du, ja = (vmin - v0) / dv, jb = (vmax - v0) / dv;
+  if (ia > ib) {
+    const double t = ia;
+    ia = ib;
+    ib = t;
+  }
+  if (ja > jb) {
+    const double t = ja;
+    ja = jb;
+    jb = t;
+  }
+  *i0 = (int)fmax(0.0, ceil(ia - 0.05));
+  *i1 = (int)fmin((double)(nu - 1), floor(ib + 0.05));
+  *j0 = (int)fmax(0.0, ceil(ja - 0.05));
+  *j1 = (int)fmin((double)(nv - 1), floor(jb + 0.05));
+}
+
+__global__ __launch_bounds__(64 * kRasterWaves) void entry_raster_kernel(MeshView M, GeomView G, int a0,
+                                                                         int32_t* entry) {
+  const int lane = threadIdx.x & 63;
+  const int group = blockIdx.x * kRasterWaves + (threadIdx.x >> 6);
+  const int a = a0 + (int)blockIdx.y;
+  const float* f = G.frame + 12 * (size_t)a;
+  const int b = group * 64 + lane;
+  int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
+  if (b < M.nb) {
+    const float4* q = M.bfaces + 4 * (size_t)b;
+    const float4 q0 = q[0], q1 = q[1], q2 = q[2];
+    raster_box(G, f, make_float3(q0.x, q0.y, q0.z), make_float3(q1.x, q1.y, q1.z), make_float3(q2.x, q2.y, q2.z),
+               &i0, &i1, &j0, &j1);
+  }
+  LaneStats st;
+  unsigned long long todo = __ballot(i0 <= i1 && j0 <= j1);
+  while (todo) {
+    const int src = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int fb = __shfl(b, src, 64), fi0 = __shfl(i0, src, 64), fi1 = __shfl(i1, src, 64);
+    const int fj0 = __shfl(j0, src, 64), fj1 = __shfl(j1, src, 64);
+    const int w = fi1 - fi0 + 1;
+    const int n = w * (fj1 - fj0 + 1);
+    for (int k = lane + 64 * (int)blockIdx.z; k < n; k += 64 * (int)gridDim.z) {
+      const int row = k / w;
+      const int i = fi0 + (k - row * w), j = fj0 + row;
+      const Ray r = cone_ray(G, M.extent, a, i, j);
+      if (enters_face(M, r, fb, st)) entry[((int64_t)a * G.nv + j) * G.nu + i] = fb;
+    }
+  }
+  flush_stats(M, st, 0);
+}
+
 // Batched problems: one persistent launch pulls pixel blocks of every
 // problem from a device work counter.  Problems are listed most expensive
 // block first, so long walks start early and short ones fill the tail.
@@ -904,6 +1023,11 @@ __global__ void fixed_finish_kernel(const unsigned long long* acc, const int* sc
 }
 
 __global__ void fill_f32_kernel(float* p, int64_t n, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
@@ -1073,6 +1197,26 @@ tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* 
   (void)hipFreeAsync(scratch, s);
   if (e != hipSuccess) return hip_fail(e, "reproducible scatter launch");
   return st;
+}
+
+tct_status entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry, hipStream_t s) {
+  const int64_t nrays = (int64_t)g->na * g->cone.nu * g->cone.nv;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, s, entry, nrays, -1);
+  if (m->nb > 0) {
+    MeshView M = m->view();
+    GeomView G = g->view();
+    const unsigned gx = (unsigned)((m->nb + 64 * kRasterWaves - 1) / (64 * kRasterWaves));
+    // Split each face's box over several wavefronts when fewer than about
+    // 32 per compute unit would run otherwise.
+    const int64_t waves = (int64_t)gx * kRasterWaves * g->na;
+    const unsigned nz = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (8192 + waves - 1) / waves));
+    for (int a0 = 0; a0 < g->na; a0 += 65535) {
+      const unsigned ny = (unsigned)std::min(65535, g->na - a0);
+      hipLaunchKernelGGL(entry_raster_kernel, dim3(gx, ny, nz), dim3(64 * kRasterWaves), 0, s, M, G, a0, entry);
+    }
+  }
+  TCT_HIP(hipGetLastError());
+  return TCT_OK;
 }
 
 // ---------------------------------------------------------------- batches

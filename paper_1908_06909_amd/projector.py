@@ -180,7 +180,7 @@ class Projector:
         self.entry = None
         if cache_entry:
             self.entry = torch.empty(geom.nrays, dtype=torch.int32, device=self.device)
-            call("tct_entry", mesh.handle, geom.handle, self.entry.data_ptr(), _stream(self.device))
+            call("tct_entry_raster", mesh.handle, geom.handle, self.entry.data_ptr(), _stream(self.device))
 
     @property
     def nt(self):
@@ -258,14 +258,17 @@ class Projector:
              _stream(self.device))
         return out
 
-    def compute_entry(self, out: Optional[torch.Tensor] = None, method: str = "bvh") -> torch.Tensor:
-        """Entry face of every ray (-1: miss) through the boundary BVH or, with
-        method="rstar", the R*-tree (mesh built with rstar=True)."""
-        if method not in ("bvh", "rstar"):
+    def compute_entry(self, out: Optional[torch.Tensor] = None, method: str = "raster") -> torch.Tensor:
+        """Entry face of every ray (-1: miss) by projecting the boundary faces
+        onto the detector (the default), through the boundary BVH
+        (method="bvh") or the R*-tree (method="rstar", mesh built with
+        rstar=True); all three give the same faces."""
+        fn = {"bvh": "tct_entry", "rstar": "tct_entry_rstar", "raster": "tct_entry_raster"}.get(method)
+        if fn is None:
             raise ValueError(f"unknown entry search {method!r}")
         if out is None:
             out = torch.empty(self.geom.nrays, dtype=torch.int32, device=self.device)
-        call("tct_entry" if method == "bvh" else "tct_entry_rstar", self.mesh.handle, self.geom.handle,
+        call(fn, self.mesh.handle, self.geom.handle,
              _ptr(out, torch.int32, self.mesh.device_index, self.geom.nrays, "entry"), _stream(self.device))
         return out
 

@@ -45,7 +45,7 @@ def _entries(w):
     mesh = tct.TetMesh(w.verts, w.tets, device=DEV, rstar=True)
     geom = tct.ConeGeometry(w.cone, w.angles, device=DEV)
     P = tct.Projector(mesh, geom, cache_entry=False)
-    eb = P.compute_entry()
+    eb = P.compute_entry(method="bvh")
     er = P.compute_entry(method="rstar")
     torch.cuda.synchronize()
     st = mesh.stats(reset=True, check=True)
