@@ -47,6 +47,22 @@ namespace {
 constexpr float kFilterRel = 10.0f * 5.9604644775390625e-8f;
 constexpr float kFilterAbs = 7.888609052210118e-31f;  // 2^-100
 
+// Walk filter.  With w = fl(d_hi x D) and e = fl(a - v), the exact edge value
+// E(v, a) = (a - v) . (d x (v - S)) = (a - v) . (d x (v - Q)) differs from
+// fl(e . w) by at most |e|_1 |d|_inf (20.5 u |D|_inf + 57.2 u^2 R): six
+// roundings per monomial of e.(d_hi x D), the d_lo x D term, and the error of
+// D itself.  The constants below (24 u, 64 u^2) leave room for the rounding of
+// the bound's own evaluation.
+constexpr float kWalkRel = 24.0f * 5.9604644775390625e-8f;
+
+// cos^2 of the angle between the ray and a face normal below which the
+// crossing is recomputed in float64.  With the vertex offset D accurate to a
+// few ulps of |D| (walk_ray), the float32 crossing moves by about c u h / cos
+// (h the face diameter, c ~ 5 from the rounded normal), i.e. 2e-5 h at
+// cos = 1/64, the same absolute size as the rounding of the float32 ray
+// parameter for the element sizes met in practice.
+constexpr float kGrazingCos2 = 1.0f / 4096.0f;
+
 struct Ray {
   float3 S, P, U, V;
   float3 d;    // d_hi = fl(P - S)
@@ -54,9 +70,9 @@ struct Ray {
   double dx64, dy64, dz64;  // P - S (exact in float64)
   double Mx64, My64, Mz64;  // the ray point at t = 1/2
   float dn;    // |d| (Euclidean)
-  float dd;    // |d|^2
-  float dinf;  // max |d_i|
-  float kR;    // 64 u^2 R, R bounding every coordinate met on this ray (walk filter)
+  float gdd;   // |d|^2 / 4096 (grazing test)
+  float kA;    // |d|_inf 24 u        walk filter: K = kA |D|_inf + kB
+  float kB;    // |d|_inf 64 u^2 R, R bounding every coordinate met on this ray
 };
 
 // Per-lane walk statistics (events of one ray; reduced per wave at the end).
@@ -84,13 +100,15 @@ __device__ __forceinline__ void finish_ray(Ray& r, float mesh_extent) {
   r.My64 = r.S.y + 0.5 * r.dy64;
   r.Mz64 = r.S.z + 0.5 * r.dz64;
   r.ad = f3abs(r.d);
-  r.dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
-  r.dn = sqrtf(r.dd);
-  r.dinf = fmaxf(r.ad.x, fmaxf(r.ad.y, r.ad.z));
+  const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
+  r.dn = sqrtf(dd);
+  r.gdd = kGrazingCos2 * dd;  // exact: a power of two
+  const float dinf = fmaxf(r.ad.x, fmaxf(r.ad.y, r.ad.z));
   float sp = fmaxf(fmaxf(fmaxf(fabsf(r.S.x), fabsf(r.S.y)), fmaxf(fabsf(r.S.z), fabsf(r.P.x))),
                    fmaxf(fabsf(r.P.y), fabsf(r.P.z)));
-  float R = (fmaxf(sp, mesh_extent) + r.dinf) * 1.0001f;
-  r.kR = 64.0f * 3.552713678800501e-15f * R;  // 64 u^2 R with u = 2^-24
+  float R = (fmaxf(sp, mesh_extent) + dinf) * 1.0001f;
+  r.kA = dinf * kWalkRel;
+  r.kB = dinf * (64.0f * 3.552713678800501e-15f * R);  // |d|_inf 64 u^2 R with u = 2^-24
 }
 
 // Pixel ray S -> P(u, v) of one angle's frame.
@@ -144,13 +162,6 @@ __device__ __noinline__ double crossing_s_fp64(float3 S, float3 P, float3 on, fl
   return (ox * nx + oy * ny + oz * nz) / (dx * nx + dy * ny + dz * nz) - 0.5;
 }
 
-// cos^2 of the angle between the ray and a face normal below which the
-// crossing is recomputed in float64.  With the vertex offset D accurate to a
-// few ulps of |D| (walk_ray), the float32 crossing moves by about c u h / cos
-// (h the face diameter, c ~ 5 from the rounded normal), i.e. 2e-5 h at
-// cos = 1/64, the same absolute size as the rounding of the float32 ray
-// parameter for the element sizes met in practice.
-constexpr float kGrazingCos2 = 1.0f / 4096.0f;
 
 // D = v - Q for the ray point Q = M + s d, in float64: M, v - M and the
 // fused s d term each carry one float64 rounding of the source-distance
@@ -163,13 +174,6 @@ __device__ __forceinline__ float3 offset_from_ray(const Ray& r, float s, float3 
                      (float)fma(-sd, r.dz64, (double)v.z - r.Mz64));
 }
 
-// Walk filter.  With w = fl(d_hi x D) and e = fl(a - v), the exact edge value
-// E(v, a) = (a - v) . (d x (v - S)) = (a - v) . (d x (v - Q)) differs from
-// fl(e . w) by at most |e|_1 |d|_inf (20.5 u |D|_inf + 57.2 u^2 R): six
-// roundings per monomial of e.(d_hi x D), the d_lo x D term, and the error of
-// D itself.  The constants below (24 u, 64 u^2) leave room for the rounding of
-// the bound's own evaluation.
-constexpr float kWalkRel = 24.0f * 5.9604644775390625e-8f;
 
 __device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, LaneStats& st) {
   if (fast != 2) return fast;
@@ -465,7 +469,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   const float3 v = w.v;
   float3 D = offset_from_ray(r, w.s_in, v);
   float3 wv = f3cross(r.d, D);
-  float K = r.dinf * (kWalkRel * fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))) + r.kR);
+  float K = fmaf(fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))), r.kA, r.kB);
   float3 e0 = f3sub(w.a0, v), e1 = f3sub(w.a1, v), e2 = f3sub(w.a2, v);
   const float E0 = f3dot(e0, wv), E1 = f3dot(e1, wv), E2 = f3dot(e2, wv);
   const float m0 = fabsf(E0) - fmaf(fabsf(e0.x) + fabsf(e0.y) + fabsf(e0.z), K, kFilterAbs);
@@ -496,7 +500,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   float3 n = f3cross(ei, ej);
   float den = f3dot(r.d, n);
   float dt;
-  if (den * den >= kGrazingCos2 * r.dd * f3dot(n, n)) {
+  if (den * den >= r.gdd * f3dot(n, n)) {
     dt = f3dot(D, n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
   } else {
     st.add_grazing();
