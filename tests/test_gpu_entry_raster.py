@@ -41,6 +41,14 @@ def _workload(name):
         w = synth.jittered_kuhn(5, 7, 8, 37, 29, 5)
         w.cone = synth.Cone(4.0, 8.0, 37, 29, 0.08, 0.09, 0.013, -0.021)  # wider than the mesh shadow
         return w
+    if name == "coplanar":
+        # The source lies (to float rounding) in the planes of whole sides of
+        # the cube: rays meet those faces edge-on, the projections of the
+        # faces collapse to segments, and the perturbed signs decide.
+        w = synth.plain_kuhn(8, 4, 64, 64, 4, pitch=2.0 ** -5)
+        th = float(np.arcsin(0.5 / 4.0))
+        w.angles = np.array([th, np.pi - th, np.pi + th, 0.5 * np.pi - th])
+        return w
     if name == "one_pixel":
         w = synth.jittered_kuhn(3, 2, 3, 1, 1, 3)
         w.cone = synth.Cone(4.0, 8.0, 1, 1, 0.05, 0.05, 0.01, 0.02)
@@ -67,7 +75,8 @@ def _compare(name):
     return hits, eb.numel()
 
 
-@pytest.mark.parametrize("name", ["cfg0", "delaunay", "delaunay_near", "graded", "ties", "ragged", "one_pixel"])
+@pytest.mark.parametrize("name", ["cfg0", "delaunay", "delaunay_near", "graded", "ties", "ragged", "one_pixel",
+                                  "coplanar"])
 def test_raster_entry_equals_bvh(name):
     hits, n = _compare(name)
     assert hits > 0
@@ -79,3 +88,41 @@ def test_raster_entry_equals_bvh(name):
 def test_raster_entry_equals_bvh_full_size(name):
     hits, _ = _compare(name)
     assert hits > 0
+
+
+def test_coplanar_source_entry_and_forward_match_oracle():
+    """Source in the planes of boundary faces: the entry face's owner is the
+    oracle's first tetrahedron on every ray, and the forward projection
+    through the boundary-projection entry cache matches the oracle's."""
+    import oracle
+    import paper_1908_06909_amd as tct
+
+    w = _workload("coplanar")
+    mesh = tct.TetMesh(w.verts, w.tets, device=DEV)
+    geom = tct.ConeGeometry(w.cone, w.angles, device=DEV)
+    P = tct.Projector(mesh, geom)  # entry cache by boundary projection
+    x = mesh.to_internal(torch.as_tensor(w.x, device=DEV))
+    got = P.forward(x).reshape(-1).cpu().numpy().astype(np.float64)
+    e = P.entry.cpu().numpy()
+    torch.cuda.synchronize()
+    st = mesh.stats(reset=True, check=True)
+    assert st["failed"] == 0
+    orc = oracle.Oracle(w.verts, w.tets, w.cone, w.angles)
+    ids = np.arange(orc.nrays)
+    _, owner = mesh.boundary()
+    trace = orc.trace(ids)
+    tv = np.zeros(len(ids))
+    for rid, (tt, _) in enumerate(trace):
+        if e[rid] < 0:
+            assert len(tt) == 0, rid
+        else:
+            assert len(tt) > 0 and owner[e[rid]] == tt[0], rid
+            xs = np.concatenate([[0.0], w.x[tt].astype(np.float64), [0.0]])
+            tv[rid] = np.abs(np.diff(xs)).sum()
+    ref = orc.forward(w.x, ids)
+    S, Pp, _, _ = orc.rays(ids)
+    tol = 1e-5 * orc.forward(np.abs(w.x), ids) + 1e-5 * np.linalg.norm(Pp.astype(np.float64) - S, axis=1) / 64 * tv
+    err = np.abs(got - ref)
+    print(f"coplanar: {int((e >= 0).sum())} rays enter; {st['perturbed_ties']} perturbed ties; "
+          f"worst err/tol {float(np.max(err / np.maximum(tol, 1e-300))):.3f}")
+    assert (err <= tol + 1e-30).all()
