@@ -5,10 +5,13 @@
 // "separating the rays" was slower on its GPU; the atomic path (walk.hip) is
 // the fast one here too.  This path trades speed for reproducibility.  Per
 // chunk of angles:
-//   1. count walk: positive-length visits per ray;
-//   2. exclusive scan -> each ray's slot range;
-//   3. fill walk: (tetrahedron, a_ij y_j) pairs in ray order;
-//   4. stable LSD radix sort by tetrahedron (ray order kept within a key);
+//   1. count walk: positive-length visits per ray, reduced to the longest
+//      list of each wavefront;
+//   2. exclusive scan -> each wavefront's slot range (64 x its longest list);
+//   3. fill walk: (tetrahedron, a_ij y_j) pairs, segment k of lane l at
+//      base + 64 k + l, so each step stores 64 consecutive words; shorter
+//      lists padded with key nt;
+//   4. stable LSD radix sort by tetrahedron (slot order kept within a key);
 //   5. one wavefront per tetrahedron sums its run in float64 (lane l takes
 //      elements l, l+64, ... in order, then a fixed butterfly), added to a
 //      float64 accumulator; chunks are added in angle order.
@@ -121,18 +124,18 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
   TCT_HIP(acc.ensure(m->nt));
   hipLaunchKernelGGL(zero_f64_kernel, dim3((m->nt + 255) / 256), dim3(256), 0, s, acc.p, (int64_t)m->nt);
   TCT_HIP(hipGetLastError());
-  const int bits = key_bits(m->nt);
+  const int bits = key_bits(m->nt + 1);  // padding key nt included
   const int a_end = a_begin + a_count;
   for (int a0 = a_begin; a0 < a_end; a0 += chunk) {
     int na_c = std::min(chunk, a_end - a0);
-    int64_t nr = (int64_t)na_c * rays_per_angle;
-    TCT_HIP(counts.ensure(nr));
-    TCT_HIP(offsets.ensure(nr + 1));
+    const int64_t nw = pixel_walk_waves(g, na_c, tile_u);
+    TCT_HIP(counts.ensure(nw));
+    TCT_HIP(offsets.ensure(nw + 1));
     tct_status st = launch_pixel_walk(kModeCountPos, m, g, a0, na_c, entry, proj, nullptr, nullptr, counts.p,
                                       nullptr, nullptr, nullptr, tile_u, s);
     if (st != TCT_OK) return st;
     int64_t total = 0;
-    st = exclusive_scan_i64(counts.p, offsets.p, nr, &total, s);
+    st = exclusive_scan_i64(counts.p, offsets.p, nw, &total, s);
     if (st != TCT_OK) return st;
     if (total == 0) continue;
     TCT_HIP(keys.ensure(total));

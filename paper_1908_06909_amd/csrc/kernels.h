@@ -32,6 +32,8 @@ tct_status launch_list_walk(int mode, const tct_mesh* m, const tct_geom* g, cons
                             const int64_t* offsets, int32_t* tets, float* lens, hipStream_t s);
 
 tct_status launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// Wavefronts of a pixel-walk launch over na_chunk angles (four per block).
+int64_t pixel_walk_waves(const tct_geom* g, int na_chunk, int tile_u);
 tct_status entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry, hipStream_t s);
 tct_status launch_permute(const float* in, float* out, const int32_t* perm, int n, int scatter, hipStream_t s);
 

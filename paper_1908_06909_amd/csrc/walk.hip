@@ -535,7 +535,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     if (dt > 0.f) {
       o.out_tet[o.cursor] = tet;
       o.out_len[o.cursor] = dt * o.weight;
-      o.cursor++;
+      o.cursor += 64;  // lists interleaved by lane within the wavefront
     }
   }
   // Keep the record one 16-byte load consumed here; otherwise the compiler
@@ -638,8 +638,9 @@ struct BlockIO {
 //   kModeBackAtomic: xhat[i] += a_ij y_j through the block's LDS table
 //   kModeBackFixed:  acc64[i] += a_ij y_j 2^scale_exp, exact integer sums
 //   kModeBackDirect: xhat[i] += a_ij y_j, one global atomic per segment
-//   kModeCountPos:   counts[rid - rid0] = positive-length visits
-//   kModeGatherFill: keys/vals at offsets[rid - rid0]
+//   kModeCountPos:   counts[wave] = 64 x the wavefront's longest list of
+//                    positive-length visits
+//   kModeGatherFill: keys/vals at offsets[wave] + 64 k + lane, padded
 // Every thread of the block must call it (the backprojection synchronises).
 template <int MODE, bool kLeanSrc = false>
 __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G, const TileMap& tm, int64_t block,
@@ -711,9 +712,8 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       __syncthreads();
       if (!any) break;
     }
-  } else if (active) {
+  } else if (active && MODE != kModeCountPos && MODE != kModeGatherFill) {
     int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
-    int64_t rid0 = (int64_t)a0 * G.nv * G.nu;
     Ray r = cone_ray(G, M.extent, a, i, j);
     // The single-problem walks have registers to spare, so their exact paths
     // read the ray from registers; the batched ones (and the windowed
@@ -741,17 +741,42 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       o.xhat = io.out_f32;
       o.weight = io.in[rid] * r.dn;
       if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, q, e, o, st);
-    } else if constexpr (MODE == kModeCountPos) {
-      WalkOut<MODE> o;
-      if (e >= 0) walk_ray<MODE>(M, r, q, e, o, st);
-      io.counts[rid - rid0] = o.count;
-    } else if constexpr (MODE == kModeGatherFill) {
-      WalkOut<MODE> o;
-      o.weight = io.in[rid] * r.dn;
+    }
+  }
+  if constexpr (MODE == kModeCountPos || MODE == kModeGatherFill) {
+    // Gather lists, laid out per wavefront so that every step's stores are
+    // 64 consecutive words: segment k of lane l at base_w + 64 k + l, the
+    // wavefront taking 64 x (its longest list) slots; shorter lists are
+    // padded with key nt (sorted after every tetrahedron) and value 0.
+    // kModeCountPos writes the wavefront's slot count, kModeGatherFill the
+    // lists at the scanned bases.  Every lane of the wavefront takes part.
+    const int64_t wave = block * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    WalkOut<MODE> o;
+    if constexpr (MODE == kModeGatherFill) {
       o.out_tet = io.keys;
       o.out_len = io.vals;
-      o.cursor = io.offsets[rid - rid0];
+      o.cursor = io.offsets[wave] + lane;
+    }
+    if (active) {
+      const int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
+      const Ray r = cone_ray(G, M.extent, a, i, j);
+      const RegSrc q{r.S, r.P, r.U, r.V};
+      const int e = io.entry ? io.entry[rid] : find_entry(M, r, st);
+      if constexpr (MODE == kModeGatherFill) o.weight = io.in[rid] * r.dn;
       if (e >= 0) walk_ray<MODE>(M, r, q, e, o, st);
+    }
+    if constexpr (MODE == kModeCountPos) {
+      int c = (int)o.count;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) c = max(c, __shfl_xor(c, off, 64));
+      if (lane == 0) io.counts[wave] = 64 * (int64_t)c;
+    } else {
+      const int64_t end = io.offsets[wave + 1];
+      for (int64_t p = o.cursor; p < end; p += 64) {
+        io.keys[p] = M.nt;
+        io.vals[p] = 0.f;
+      }
     }
   }
   flush_stats(M, st, active ? 1 : 0);
@@ -1055,6 +1080,11 @@ static TileMap make_tiles(const GeomView& g, int tile_u) {
   t.nbu = (g.nu + 2 * t.tu - 1) / (2 * t.tu);
   t.nbv = (g.nv + 2 * t.tv - 1) / (2 * t.tv);
   return t;
+}
+
+int64_t pixel_walk_waves(const tct_geom* g, int na_chunk, int tile_u) {
+  const TileMap tm = make_tiles(g->view(), tile_u);
+  return (int64_t)tm.nbu * tm.nbv * na_chunk * 4;
 }
 
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
