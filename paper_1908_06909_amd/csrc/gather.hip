@@ -1,10 +1,10 @@
 // Deterministic backprojection: xhat_i = sum_j a_ij y_j (Eq. 3) summed per
 // tetrahedron in a fixed order, so the result is bitwise reproducible.
 //
-// The paper scatters with atomics (Section II-F) and reports that
-// "separating the rays" was slower on its GPU; the atomic path (walk.hip) is
-// the fast one here too.  This path trades speed for reproducibility.  Per
-// chunk of angles:
+// The paper scatters with atomics (Section II-F), having found a variant
+// that kept the rays' contributions apart slower on its GPU; the atomic path
+// (walk.hip) is the fast one here too.  This path trades speed for
+// reproducibility.  Per chunk of angles:
 //   1. count walk: positive-length visits per ray, reduced to the longest
 //      list of each wavefront;
 //   2. exclusive scan -> each wavefront's slot range (64 x its longest list);
@@ -12,9 +12,10 @@
 //      base + 64 k + l, so each step stores 64 consecutive words; shorter
 //      lists padded with key nt;
 //   4. stable LSD radix sort by tetrahedron (slot order kept within a key);
-//   5. one wavefront per tetrahedron sums its run in float64 (lane l takes
-//      elements l, l+64, ... in order, then a fixed butterfly), added to a
-//      float64 accumulator; chunks are added in angle order.
+//   5. run boundaries from the sorted keys; one wavefront per tetrahedron
+//      sums its run in float64 (lane l takes elements l, l+64, ... in order,
+//      then a fixed butterfly), added to a float64 accumulator; chunks are
+//      added in angle order.
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -30,29 +31,30 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-__device__ __forceinline__ int64_t lower_bound_key(const int32_t* keys, int64_t n, int32_t k) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (keys[mid] < k)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
+__global__ void zero_i64_kernel(int64_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Run boundaries of the sorted keys: [run[2 t], run[2 t + 1]) holds
+// tetrahedron t (both zero when it has no segment); padding keys (>= nt)
+// are skipped.
+__global__ void run_bounds_kernel(const int32_t* keys, int64_t n, int nt, int64_t* run) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = keys[i];
+  if (k >= nt) return;
+  if (i == 0 || keys[i - 1] != k) run[2 * (int64_t)k] = i;
+  if (i == n - 1 || keys[i + 1] != k) run[2 * (int64_t)k + 1] = i + 1;
 }
 
 // One wavefront per tetrahedron.
-__global__ __launch_bounds__(256) void segment_sum_kernel(const int32_t* keys, const float* vals, int64_t n,
-                                                          double* acc, int nt) {
+__global__ __launch_bounds__(256) void segment_sum_kernel(const int64_t* run, const float* vals, double* acc,
+                                                          int nt) {
   int t = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   int lane = threadIdx.x & 63;
   if (t >= nt) return;
-  int64_t b = 0, e = 0;
-  if (lane == 0) b = lower_bound_key(keys, n, t);
-  if (lane == 1) e = lower_bound_key(keys, n, t + 1);
-  b = __shfl(b, 0, 64);
-  e = __shfl(e, 1, 64);
+  const int64_t b = run[2 * (int64_t)t], e = run[2 * (int64_t)t + 1];
   if (b == e) return;
   double s = 0.0;
   for (int64_t i = b + lane; i < e; i += 64) s += (double)vals[i];
@@ -121,7 +123,9 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
   AsyncBuf<int32_t> keys(s), keys_sorted(s);
   AsyncBuf<float> vals(s), vals_sorted(s);
   AsyncBuf<char> sort_tmp(s);
+  AsyncBuf<int64_t> run(s);
   TCT_HIP(acc.ensure(m->nt));
+  TCT_HIP(run.ensure(2 * (size_t)m->nt));
   hipLaunchKernelGGL(zero_f64_kernel, dim3((m->nt + 255) / 256), dim3(256), 0, s, acc.p, (int64_t)m->nt);
   TCT_HIP(hipGetLastError());
   const int bits = key_bits(m->nt + 1);  // padding key nt included
@@ -151,9 +155,13 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
     TCT_HIP(sort_tmp.ensure(tmp_bytes));
     TCT_HIP(rocprim::radix_sort_pairs(sort_tmp.p, tmp_bytes, keys.p, keys_sorted.p, vals.p, vals_sorted.p,
                                       (size_t)total, 0, bits, s));
+    const int64_t nrun = 2 * (int64_t)m->nt;
+    hipLaunchKernelGGL(zero_i64_kernel, dim3((unsigned)((nrun + 255) / 256)), dim3(256), 0, s, run.p, nrun);
+    hipLaunchKernelGGL(run_bounds_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, keys_sorted.p,
+                       total, m->nt, run.p);
     int64_t threads = (int64_t)m->nt * 64;
-    hipLaunchKernelGGL(segment_sum_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, keys_sorted.p,
-                       vals_sorted.p, total, acc.p, m->nt);
+    hipLaunchKernelGGL(segment_sum_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, run.p,
+                       vals_sorted.p, acc.p, m->nt);
     TCT_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(finish_kernel, dim3((m->nt + 255) / 256), dim3(256), 0, s, acc.p, xhat, m->nt, accumulate);
