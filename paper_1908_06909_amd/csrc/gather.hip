@@ -39,13 +39,25 @@ __global__ void zero_i64_kernel(int64_t* p, int64_t n) {
 // Run boundaries of the sorted keys: [run[2 t], run[2 t + 1]) holds
 // tetrahedron t (both zero when it has no segment); padding keys (>= nt)
 // are skipped.
+// Each thread takes kRunItems consecutive keys.
+constexpr int kRunItems = 8;
+
 __global__ void run_bounds_kernel(const int32_t* keys, int64_t n, int nt, int64_t* run) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int k = keys[i];
-  if (k >= nt) return;
-  if (i == 0 || keys[i - 1] != k) run[2 * (int64_t)k] = i;
-  if (i == n - 1 || keys[i + 1] != k) run[2 * (int64_t)k + 1] = i + 1;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRunItems;
+  if (i0 >= n) return;
+  int prev = i0 > 0 ? keys[i0 - 1] : -1;
+#pragma unroll
+  for (int u = 0; u < kRunItems; ++u) {
+    const int64_t i = i0 + u;
+    if (i >= n) break;
+    const int k = keys[i];
+    const int next = i + 1 < n ? keys[i + 1] : -1;
+    if (k < nt) {
+      if (prev != k) run[2 * (int64_t)k] = i;
+      if (next != k) run[2 * (int64_t)k + 1] = i + 1;
+    }
+    prev = k;
+  }
 }
 
 // One wavefront per tetrahedron.
@@ -157,8 +169,9 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
                                       (size_t)total, 0, bits, s));
     const int64_t nrun = 2 * (int64_t)m->nt;
     hipLaunchKernelGGL(zero_i64_kernel, dim3((unsigned)((nrun + 255) / 256)), dim3(256), 0, s, run.p, nrun);
-    hipLaunchKernelGGL(run_bounds_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, keys_sorted.p,
-                       total, m->nt, run.p);
+    const int64_t run_threads = (total + kRunItems - 1) / kRunItems;
+    hipLaunchKernelGGL(run_bounds_kernel, dim3((unsigned)((run_threads + 255) / 256)), dim3(256), 0, s,
+                       keys_sorted.p, total, m->nt, run.p);
     int64_t threads = (int64_t)m->nt * 64;
     hipLaunchKernelGGL(segment_sum_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, run.p,
                        vals_sorted.p, acc.p, m->nt);
