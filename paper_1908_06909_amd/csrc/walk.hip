@@ -472,15 +472,20 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   float K = fmaf(fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))), r.kA, r.kB);
   float3 e0 = f3sub(w.a0, v), e1 = f3sub(w.a1, v), e2 = f3sub(w.a2, v);
   const float E0 = f3dot(e0, wv), E1 = f3dot(e1, wv), E2 = f3dot(e2, wv);
-  const float m0 = fabsf(E0) - fmaf(fabsf(e0.x) + fabsf(e0.y) + fabsf(e0.z), K, kFilterAbs);
-  const float m1 = fabsf(E1) - fmaf(fabsf(e1.x) + fabsf(e1.y) + fabsf(e1.z), K, kFilterAbs);
-  const float m2 = fabsf(E2) - fmaf(fabsf(e2.x) + fabsf(e2.y) + fabsf(e2.z), K, kFilterAbs);
+  const float l0 = fabsf(e0.x) + fabsf(e0.y) + fabsf(e0.z);
+  const float l1 = fabsf(e1.x) + fabsf(e1.y) + fabsf(e1.z);
+  const float l2 = fabsf(e2.x) + fabsf(e2.y) + fabsf(e2.z);
+  // One bound from the longest edge settles all three signs in the common
+  // case; otherwise each edge gets its own bound before any float64 work.
   int k;
-  if (fminf(m0, fminf(m1, m2)) > 0.f) {
+  if (fminf(fabsf(E0), fminf(fabsf(E1), fabsf(E2))) > fmaf(fmaxf(l0, fmaxf(l1, l2)), K, kFilterAbs)) {
     const unsigned n = (__float_as_uint(E0) >> 31) | ((__float_as_uint(E1) >> 31) << 1) |
                        ((__float_as_uint(E2) >> 31) << 2);
     k = (int)((kExitFace >> (2 * n)) & 3u);
   } else {
+    const float m0 = fabsf(E0) - fmaf(l0, K, kFilterAbs);
+    const float m1 = fabsf(E1) - fmaf(l1, K, kFilterAbs);
+    const float m2 = fabsf(E2) - fmaf(l2, K, kFilterAbs);
     const int s0 = m0 > 0.f ? (E0 > 0.f ? 1 : -1) : resolve_src(q, v, w.a0, st);
     const int s1 = m1 > 0.f ? (E1 > 0.f ? 1 : -1) : resolve_src(q, v, w.a1, st);
     const int s2 = m2 > 0.f ? (E2 > 0.f ? 1 : -1) : resolve_src(q, v, w.a2, st);
