@@ -883,10 +883,11 @@ __device__ __forceinline__ void raster_box(const GeomView& G, const float* f, fl
     ja = jb;
     jb = t;
   }
-  *i0 = (int)fmax(0.0, ceil(ia - 0.05));
-  *i1 = (int)fmin((double)(nu - 1), floor(ib + 0.05));
-  *j0 = (int)fmax(0.0, ceil(ja - 0.05));
-  *j1 = (int)fmin((double)(nv - 1), floor(jb + 0.05));
+  // Clamped in double before the conversion, so far-off boxes stay empty.
+  *i0 = (int)fmin((double)nu, fmax(0.0, ceil(ia - 0.05)));
+  *i1 = (int)fmax(-1.0, fmin((double)(nu - 1), floor(ib + 0.05)));
+  *j0 = (int)fmin((double)nv, fmax(0.0, ceil(ja - 0.05)));
+  *j1 = (int)fmax(-1.0, fmin((double)(nv - 1), floor(jb + 0.05)));
 }
 
 __global__ __launch_bounds__(64 * kRasterWaves) void entry_raster_kernel(MeshView M, GeomView G, int a0,
@@ -911,12 +912,22 @@ __global__ __launch_bounds__(64 * kRasterWaves) void entry_raster_kernel(MeshVie
     const int fb = __shfl(b, src, 64), fi0 = __shfl(i0, src, 64), fi1 = __shfl(i1, src, 64);
     const int fj0 = __shfl(j0, src, 64), fj1 = __shfl(j1, src, 64);
     const int w = fi1 - fi0 + 1;
-    const int n = w * (fj1 - fj0 + 1);
-    for (int k = lane + 64 * (int)blockIdx.z; k < n; k += 64 * (int)gridDim.z) {
-      const int row = k / w;
-      const int i = fi0 + (k - row * w), j = fj0 + row;
-      const Ray r = cone_ray(G, M.extent, a, i, j);
-      if (enters_face(M, r, fb, st)) entry[((int64_t)a * G.nv + j) * G.nu + i] = fb;
+    const int64_t n = (int64_t)w * (fj1 - fj0 + 1);
+    const int z = (int)blockIdx.z, nz = (int)gridDim.z;
+    if (n < 0x7fff0000) {  // 32-bit indices (k + 64 gridDim.z cannot overflow) unless the box is huge
+      for (int k = lane + 64 * z; k < (int)n; k += 64 * nz) {
+        const int row = k / w;
+        const int i = fi0 + (k - row * w), j = fj0 + row;
+        const Ray r = cone_ray(G, M.extent, a, i, j);
+        if (enters_face(M, r, fb, st)) entry[((int64_t)a * G.nv + j) * G.nu + i] = fb;
+      }
+    } else {
+      for (int64_t k = lane + 64 * z; k < n; k += 64 * nz) {
+        const int64_t row = k / w;
+        const int i = fi0 + (int)(k - row * w), j = fj0 + (int)row;
+        const Ray r = cone_ray(G, M.extent, a, i, j);
+        if (enters_face(M, r, fb, st)) entry[((int64_t)a * G.nv + j) * G.nu + i] = fb;
+      }
     }
   }
   flush_stats(M, st, 0);
