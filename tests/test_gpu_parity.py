@@ -561,3 +561,61 @@ def test_delaunay_sequences_projection_and_backprojections():
         bp = c.to_user(c.P.backproject(torch.as_tensor(y, device=DEV), mode=mode)).astype(np.float64)
         assert_within(bp, ref_bp, tol, f"delaunay backprojection {mode}")
     check_stats(c.mesh)
+
+
+def _candidate_rays(c, tet_ids):
+    """Every ray whose pixel centre lies in the bounding box of a listed
+    tetrahedron's central projection (widened by a hundredth of a pixel):
+    a superset of the rays that cross it, computed in float64 from the
+    oracle's frames, independent of the GPU path."""
+    S, D, U, V, ut, vt = oracle.frame(c.w.cone, c.w.angles)
+    nu, nv, na = c.w.cone.nu, c.w.cone.nv, len(c.w.angles)
+    du = (float(ut[-1]) - float(ut[0])) / (nu - 1)
+    dv = (float(vt[-1]) - float(vt[0])) / (nv - 1)
+    per_tet = []
+    for t in tet_ids:
+        P4 = c.w.verts[c.w.tets[t]].astype(np.float64)
+        ids = []
+        for a in range(na):
+            s, d, u, v = (x[a].astype(np.float64) for x in (S, D, U, V))
+            N = np.cross(u, v)
+            rel = P4 - s
+            X = s + ((d - s) @ N / (rel @ N))[:, None] * rel - d
+            uu, vv = X @ u / (u @ u), X @ v / (v @ v)
+            i0 = max(0, int(np.ceil((uu.min() - ut[0]) / du - 0.01)))
+            i1 = min(nu - 1, int(np.floor((uu.max() - ut[0]) / du + 0.01)))
+            j0 = max(0, int(np.ceil((vv.min() - vt[0]) / dv - 0.01)))
+            j1 = min(nv - 1, int(np.floor((vv.max() - vt[0]) / dv + 0.01)))
+            if i0 > i1 or j0 > j1:
+                continue
+            jj, ii = np.meshgrid(np.arange(j0, j1 + 1), np.arange(i0, i1 + 1), indexing="ij")
+            ids.append(((a * nv + jj) * nu + ii).ravel())
+        per_tet.append(np.concatenate(ids))
+    return per_tet
+
+
+def test_cfg1_sampled_backprojection_against_oracle():
+    """Full-size backprojections in the launch the benchmark times, checked
+    element by element against the oracle on sampled tetrahedra: the oracle
+    backprojects only the rays whose pixels lie under each sampled element's
+    shadow, which contains every ray that crosses it, so its value for that
+    element is exact."""
+    c = case("cfg1")
+    rng = np.random.default_rng(12)
+    tets = rng.choice(c.orc.nt, 2, replace=False)
+    per_tet = _candidate_rays(c, tets)
+    ids = np.unique(np.concatenate(per_tet))
+    y = rng.uniform(0.0, 1.0, c.orc.nrays).astype(f32)
+    ref = c.orc.backproject(y[ids], ids)[tets]
+    yd = torch.as_tensor(y, device=DEV)
+    for mode in ("atomic", "fixed", "shadow"):
+        got = c.to_user(c.P.backproject(yd, mode=mode))[tets].astype(np.float64)
+        # y >= 0: a float32 sum of n non-negative terms errs by at most
+        # n 2^-24 of the sum (the candidate count bounds n); float64 and
+        # exact integer sums only by the final rounding.
+        n = np.array([len(p) for p in per_tet], np.float64)
+        rel = 1e-5 + (n * 2.0 ** -24 if mode == "atomic" else 2.0 ** -23)
+        err = np.abs(got - ref)
+        print(f"cfg1 sampled {mode} backprojection: values {ref}, rel err {err / ref}")
+        assert np.all(err <= rel * ref), (mode, got, ref)
+    check_stats(c.mesh)
