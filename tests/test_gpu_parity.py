@@ -596,8 +596,9 @@ def _candidate_rays(c, tet_ids):
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2"])
 def test_full_size_sampled_backprojection_against_oracle(name):
-    """Full-size backprojections in the launch the benchmark times, checked
-    element by element against the oracle on sampled tetrahedra: the oracle
+    """Full-size backprojections (every mode, the scatter in the launch the
+    benchmark times), checked element by element against the oracle on
+    sampled tetrahedra: the oracle
     backprojects only the rays whose pixels lie under each sampled element's
     shadow, which contains every ray that crosses it, so its value for that
     element is exact."""
@@ -619,9 +620,9 @@ def test_full_size_sampled_backprojection_against_oracle(name):
     pos = {int(r): k for k, r in enumerate(ids)}
     walk_tol = np.array([2.0 ** -24 * float(np.sum(dlen[[pos[int(r)] for r in p]] * y[p])) for p in per_tet])
     n = np.array([len(p) for p in per_tet], np.float64)
-    for mode in ("atomic", "fixed", "shadow"):
+    for mode in ("atomic", "fixed", "shadow", "gather", "atomic_direct"):
         got = c.to_user(c.P.backproject(yd, mode=mode))[tets].astype(np.float64)
-        rel = 1e-5 + (n * 2.0 ** -24 if mode == "atomic" else 2.0 ** -23)
+        rel = 1e-5 + (n * 2.0 ** -24 if mode in ("atomic", "atomic_direct") else 2.0 ** -23)
         tol = rel * ref + (walk_tol if mode != "shadow" else 0.0)
         err = np.abs(got - ref)
         print(f"{name} sampled {mode} backprojection: values {ref}, err/tol {err / tol}")
