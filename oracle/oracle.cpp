@@ -679,7 +679,7 @@ Cone cone_from(const double* c) {
 // Readings (the same ones the library documents): v uses the dot product d . r;
 // past eps = 1 the ray halts; t1 = smallest parameter hit, the exit is the
 // face with the largest parameter other than the face the ray came in by,
-// lowest index on ties; 16384 steps at most (else "looping"); the ray enters
+// lowest index on ties; 16384 steps at most (else counted as looping); the ray enters
 // through the boundary face found exactly.  Local vertex order: ascending
 // node ids, the last two swapped if negatively oriented; face k opposite
 // vertex k, its other vertices in increasing local order.  Arithmetic in a

@@ -13,7 +13,7 @@
 //     each failure; past eps = 1 the ray is declared halted;
 //   * of the faces hit, t1 is the smallest parameter and the exit is the
 //     face with the largest one other than the face the ray came in by
-//     (never step back; the "swap" check of Algorithm 2), lowest index on
+//     (never step back; the check of Algorithm 2 that exchanges the hits), lowest index on
 //     ties;
 //   * a ray that takes more than kPaperStepCap steps is declared looping;
 //   * the ray enters through the boundary face found by the exact entry
