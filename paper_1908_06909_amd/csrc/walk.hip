@@ -168,10 +168,9 @@ __device__ __noinline__ double crossing_s_fp64(float3 S, float3 P, float3 on, fl
 // scale R, so with the final rounding to float32
 // |D - (v - Q)| <= u |D| + 2^-51 R componentwise, inside the allowance
 // 3.1 u |D| + 28 u^2 R the walk filter below is built on.
-__device__ __forceinline__ float3 offset_from_ray(const Ray& r, float s, float3 v) {
-  const double sd = (double)s;
-  return make_float3((float)fma(-sd, r.dx64, (double)v.x - r.Mx64), (float)fma(-sd, r.dy64, (double)v.y - r.My64),
-                     (float)fma(-sd, r.dz64, (double)v.z - r.Mz64));
+__device__ __forceinline__ float3 offset_from_ray(const Ray& r, double s, float3 v) {
+  return make_float3((float)fma(-s, r.dx64, (double)v.x - r.Mx64), (float)fma(-s, r.dy64, (double)v.y - r.My64),
+                     (float)fma(-s, r.dz64, (double)v.z - r.Mz64));
 }
 
 
@@ -424,7 +423,7 @@ struct WalkState {
   float3 a0, a1, a2, v;
   int tet;
   unsigned loc;
-  float s_in;
+  double s_in;  // ray parameter where the ray entered the current tetrahedron
   float xcur;  // forward projection: x of the current tetrahedron
   int steps;
 };
@@ -442,14 +441,15 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, cons
   w.a1 = make_float3(q1.x, q1.y, q1.z);
   w.a2 = make_float3(q2.x, q2.y, q2.z);
   w.v = make_float3(q3.x, q3.y, q3.z);
-  // Ray parameters are kept as s = t - 1/2 around the reference point M.  Each
-  // step forms D = v - Q for the current entry point Q = M + s_in d in
-  // float64 (offset_from_ray), so both the exit-face signs and the
-  // crossing are evaluated from a vector of element size whose error is a
-  // few ulps of itself, not of the source distance.  Only segment lengths
-  // are accumulated, never differences of rounded parameters.
-  float s_in = (float)crossing_s_fp64(q.S(), q.P(), w.a0, w.a1, w.a2);
-  w.s_in = fminf(fmaxf(s_in, -0.5f), 0.5f);
+  // Ray parameters are kept in float64 as s = t - 1/2 around the reference
+  // point M.  Each step forms D = v - Q for the current entry point
+  // Q = M + s_in d in float64 (offset_from_ray), so both the exit-face signs
+  // and the crossing are evaluated from a vector of element size whose error
+  // is a few ulps of itself, not of the source distance.  Each segment's
+  // float32 length is added to s_in in float64, so the entry points do not
+  // drift by a rounding of the parameter per step.
+  const double s_in = crossing_s_fp64(q.S(), q.P(), w.a0, w.a1, w.a2);
+  w.s_in = fmin(fmax(s_in, -0.5), 0.5);
   w.xcur = 0.f;
   if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
   w.steps = 0;
@@ -513,9 +513,9 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
                                   k2 ? w.a0.z : (k0 ? w.a1.z : w.a2.z));
     const float3 aj = make_float3(k2 ? w.a1.x : (k0 ? w.a2.x : w.a0.x), k2 ? w.a1.y : (k0 ? w.a2.y : w.a0.y),
                                   k2 ? w.a1.z : (k0 ? w.a2.z : w.a0.z));
-    dt = (float)(crossing_s_fp64(q.S(), q.P(), v, ai, aj) - (double)w.s_in);
+    dt = (float)(crossing_s_fp64(q.S(), q.P(), v, ai, aj) - w.s_in);
   }
-  dt = __builtin_amdgcn_fmed3f(dt, 0.0f, fmaxf(0.5f - w.s_in, 0.0f));
+  dt = __builtin_amdgcn_fmed3f(dt, 0.0f, (float)fmax(0.5 - w.s_in, 0.0));
   if (dt == 0.f) st.add_zero();
   // Next tetrahedron across the exit face (local face index loc[k]).
   const int tet = w.tet;
@@ -568,7 +568,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   w.loc = (((N & 0xFFFu) & ~fieldk) | ((N >> 12) << sh)) | (back << 12);
   w.v = xyz(rec);
   w.tet = packed >> 2;
-  w.s_in += dt;
+  w.s_in += (double)dt;  // float64: no rounding drift along the ray
   if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
   return true;
 }

@@ -610,11 +610,12 @@ def test_full_size_sampled_backprojection_against_oracle(name):
     y = rng.uniform(0.0, 1.0, c.orc.nrays).astype(f32)
     ref = c.orc.backproject(y[ids], ids)[tets]
     yd = torch.as_tensor(y, device=DEV)
-    # Walked segment lengths err by at most about 2^-25 |d| each (the float32
-    # ray parameter is rounded once per step), taken here as 2^-24 |d_j| y_j
-    # per candidate ray; y >= 0, so a float32 sum of n terms errs by at most
-    # n 2^-24 of the sum, and float64 or exact integer sums by their final
-    # rounding (the candidate count bounds n).
+    # Walked segment lengths are float32 crossings (a few ulps of the
+    # segment, up to 64 ulps of the element size at the grazing threshold),
+    # bounded here generously by 2^-24 |d_j| y_j per candidate ray; y >= 0,
+    # so a float32 sum of n terms errs by at most n 2^-24 of the sum, and
+    # float64 or exact integer sums by their final rounding (the candidate
+    # count bounds n).
     S, P, _, _ = c.orc.rays(ids)
     dlen = np.linalg.norm(P.astype(np.float64) - S, axis=1)
     pos = {int(r): k for k, r in enumerate(ids)}
