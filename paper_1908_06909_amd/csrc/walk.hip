@@ -58,10 +58,11 @@ constexpr float kWalkRel = 24.0f * 5.9604644775390625e-8f;
 // cos^2 of the angle between the ray and a face normal below which the
 // crossing is recomputed in float64.  With the vertex offset D accurate to a
 // few ulps of |D| (walk_ray), the float32 crossing moves by about c u h / cos
-// (h the face diameter, c ~ 5 from the rounded normal), i.e. 2e-5 h at
-// cos = 1/64, the same absolute size as the rounding of the float32 ray
-// parameter for the element sizes met in practice.
-constexpr float kGrazingCos2 = 1.0f / 4096.0f;
+// (h the face diameter, c ~ 5 from the rounded normal), i.e. 4e-5 h at
+// cos = 1/128; about one segment in ten thousand is that oblique, so the
+// bound on a projection, a sum over some hundred segments, stays near 1e-7
+// of it.
+constexpr float kGrazingCos2 = 1.0f / 16384.0f;
 
 struct Ray {
   float3 S, P, U, V;
