@@ -849,6 +849,15 @@ int orc_det_sign_exact(const float* A1, const float* A0, const float* B1, const 
   return det_sign_exact(A1, A0, B1, B0, C1, C0);
 }
 
+// The same sign for n triples of difference vectors ([n][3] arrays), for
+// checking other code's sign decisions in bulk.
+void orc_det_sign_batch(long long n, const float* A1, const float* A0, const float* B1, const float* B0,
+                        const float* C1, const float* C0, int* out) {
+#pragma omp parallel for schedule(static)
+  for (long long i = 0; i < n; ++i)
+    out[i] = det_sign(A1 + 3 * i, A0 + 3 * i, B1 + 3 * i, B0 + 3 * i, C1 + 3 * i, C0 + 3 * i);
+}
+
 int orc_edge_sign(const float* S, const float* P, const float* U, const float* V, const float* p, const float* q) {
   Ray r;
   std::memcpy(r.S, S, 12);
@@ -987,18 +996,66 @@ int orc_backproject(void* h, const double* cone, const double* angles, int na, c
   return status.load();
 }
 
+// Backprojection with the quantities tests bound its errors by, in one pass
+// over the listed rays: xhat_i = sum_j a_ij y_j, support_i = the sum of y_j
+// over the rays that cross tetrahedron i with positive length, count_i =
+// the number of those rays.  Any output may be NULL.
+int orc_backproject_ext(void* h, const double* cone, const double* angles, int na, const float* y,
+                        const long long* ids, long long n, double* xhat, double* support, double* count,
+                        int nthreads) {
+  const Mesh& m = *(const Mesh*)h;
+  Frame f = make_frame(cone_from(cone), angles, na);
+  long long total = (long long)na * f.nu * f.nv;
+  if (!ids) n = total;
+  int nth = nthreads_of(nthreads);
+  std::vector<std::vector<double>> part(nth, std::vector<double>(3 * (size_t)m.nt, 0.0));
+  std::vector<WalkStats> ws(nth);
+  std::atomic<int> status{OK};
+#pragma omp parallel for schedule(static) num_threads(nth)
+  for (long long i = 0; i < n; ++i) {
+    std::vector<Visit> path;
+    long long rid = ids ? ids[i] : i;
+    Ray r = make_ray(f, rid);
+    int tid = thread_id();
+    int st = walk(m, r, &path, &ws[tid]);
+    if (st != OK) status = st;
+    double* p = part[tid].data();
+    for (const auto& v : path) {
+      p[3 * (size_t)v.tet] += v.len * (double)y[i];
+      if (v.len > 0.0) {
+        p[3 * (size_t)v.tet + 1] += (double)y[i];
+        p[3 * (size_t)v.tet + 2] += 1.0;
+      }
+    }
+  }
+  for (int t = 0; t < m.nt; ++t) {
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < nth; ++k)
+      for (int c = 0; c < 3; ++c) s[c] += part[k][3 * (size_t)t + c];
+    if (xhat) xhat[t] = s[0];
+    if (support) support[t] = s[1];
+    if (count) count[t] = s[2];
+  }
+  g_last = WalkStats();
+  for (auto& w : ws) g_last.add(w);
+  return status.load();
+}
+
 namespace {
 int trace_common(const Mesh& m, const std::vector<Ray>& rays, long long* offsets, int* tets, double* lens,
                  long long cap) {
   long long n = (long long)rays.size();
   std::vector<std::vector<Visit>> paths(n);
-  WalkStats ws;
-  int status = OK;
+  int nth = nthreads_of(0);
+  std::vector<WalkStats> ws(nth);
+  std::atomic<int> status{OK};
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nth)
   for (long long i = 0; i < n; ++i) {
-    int st = walk(m, rays[i], &paths[i], &ws);
+    int st = walk(m, rays[i], &paths[i], &ws[thread_id()]);
     if (st != OK) status = st;
   }
-  g_last = ws;
+  g_last = WalkStats();
+  for (auto& w : ws) g_last.add(w);
   long long off = 0;
   offsets[0] = 0;
   for (long long i = 0; i < n; ++i) {
@@ -1013,7 +1070,7 @@ int trace_common(const Mesh& m, const std::vector<Ray>& rays, long long* offsets
       lens[o + k] = paths[i][k].len;
     }
   }
-  return status;
+  return status.load();
 }
 }  // namespace
 

@@ -53,6 +53,8 @@ def lib():
     for name in ("orc_det_sign", "orc_det_sign_exact", "orc_edge_sign"):
         getattr(L, name).argtypes = [_f32p] * 6
         getattr(L, name).restype = C.c_int
+    L.orc_det_sign_batch.argtypes = [C.c_longlong] + [_f32p] * 6 + [_i32p]
+    L.orc_det_sign_batch.restype = None
     L.orc_mesh_create.argtypes = [_f32p, C.c_int, _i32p, C.c_int, C.POINTER(C.c_void_p)]
     L.orc_mesh_destroy.argtypes = [C.c_void_p]
     L.orc_mesh_nboundary.argtypes = [C.c_void_p]
@@ -66,6 +68,8 @@ def lib():
                                     _f64p, _i64p, C.c_int]
     L.orc_backproject.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f32p, C.c_void_p, C.c_longlong, _f64p,
                                   C.c_int]
+    L.orc_backproject_ext.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f32p, C.c_void_p, C.c_longlong,
+                                      _f64p, _f64p, _f64p, C.c_int]
     L.orc_trace.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _i64p, C.c_longlong, _i64p, _i32p, _f64p,
                             C.c_longlong]
     L.orc_trace_rays.argtypes = [C.c_void_p, _f32p, _f32p, _f32p, _f32p, C.c_longlong, _i64p, _i32p, _f64p,
@@ -96,6 +100,16 @@ def det_sign(A1, A0, B1, B0, C1, C0) -> int:
 def det_sign_exact(A1, A0, B1, B0, C1, C0) -> int:
     """Same determinant sign, always through the big-integer path."""
     return lib().orc_det_sign_exact(*(map(_f3, (A1, A0, B1, B0, C1, C0))))
+
+
+def det_sign_batch(A1, A0, B1, B0, C1, C0) -> np.ndarray:
+    """Exact signs of det[A1-A0, B1-B0, C1-C0] for [n, 3] float32 arrays."""
+    arrs = [np.ascontiguousarray(np.asarray(a, np.float32).reshape(-1, 3)) for a in (A1, A0, B1, B0, C1, C0)]
+    n = len(arrs[0])
+    assert all(len(a) == n for a in arrs)
+    out = np.zeros(n, np.int32)
+    lib().orc_det_sign_batch(n, *arrs, out)
+    return out
 
 
 def edge_sign(S, P, U, V, p, q) -> int:
@@ -246,6 +260,19 @@ class Oracle:
                                    None if ids_a is None else ids_a.ctypes.data, n, out, self.nthreads)
         self._check(st)
         return out
+
+    def backproject_ext(self, y, ids=None):
+        """(xhat, support, count) over the listed rays: xhat_i = sum_j a_ij y_j,
+        support_i = sum of y_j over the rays j with a_ij > 0, count_i = their
+        number (the last two size error bounds in tests)."""
+        y = np.ascontiguousarray(y, dtype=np.float32).ravel()
+        ids_a, n = self._ids(ids)
+        assert len(y) == n
+        out = [np.zeros(self.nt, np.float64) for _ in range(3)]
+        st = lib().orc_backproject_ext(self.mesh._h, self._cone, self.angles, self.na, y,
+                                       None if ids_a is None else ids_a.ctypes.data, n, *out, self.nthreads)
+        self._check(st)
+        return tuple(out)
 
     def trace(self, ids):
         """List of (tets int32, lengths float64) per listed ray."""

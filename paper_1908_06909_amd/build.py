@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtetct.so")
 
 SOURCES = ["mesh.cpp", "rstar.cpp", "capi.cpp", "walk.hip", "gather.hip", "shadow.hip", "paper_mode.hip", "blas.hip"]
-HEADERS = ["common.h", "exact.h", "kernels.h", "rstar.h", os.path.join("..", "..", "include", "tetct.h")]
+HEADERS = ["common.h", "exact.h", "kernels.h", "ray.h", "rstar.h", "walk_filter.h", os.path.join("..", "..", "include", "tetct.h")]
 
 ARCH = os.environ.get("TCT_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

@@ -1,24 +1,16 @@
 // Device helpers shared by the ray walk and the element-driven
-// backprojection: small vector operations, the pixel ray endpoint and the
-// exact perturbed edge sign.  Both kernels must see identical rays and
+// backprojection: the pixel ray endpoint and the exact perturbed edge sign
+// (small vector operations come from walk_filter.h).  Both kernels must see identical rays and
 // identical signs, so they take them from here.
 #pragma once
 
 #include "common.h"
 #include "exact.h"
+#include "walk_filter.h"
 
 namespace tct {
 namespace {
 
-__device__ __forceinline__ float3 f3sub(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
-// Dot and cross products with fused multiply-adds (the library is built
-// without automatic contraction): each monomial meets no more roundings than
-// in the plain order, so the error bounds stated where they are used hold.
-__device__ __forceinline__ float f3dot(float3 a, float3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
-__device__ __forceinline__ float3 f3cross(float3 a, float3 b) {
-  return make_float3(fmaf(a.y, b.z, -(a.z * b.y)), fmaf(a.z, b.x, -(a.x * b.z)), fmaf(a.x, b.y, -(a.y * b.x)));
-}
-__device__ __forceinline__ float3 f3abs(float3 a) { return make_float3(fabsf(a.x), fabsf(a.y), fabsf(a.z)); }
 __device__ __forceinline__ float3 xyz(float4 a) { return make_float3(a.y, a.z, a.w); }
 
 // Detector point of pixel (u, v) for one angle's frame f = {S, D, U, V}:

@@ -39,43 +39,6 @@ namespace tct {
 
 namespace {
 
-// Float32 filter constants: every monomial of (q-p).((P-S)x(p-S)) carries at
-// most 8 roundings (three input differences, product and difference in the
-// cross product, the outer product, two additions); with the bound itself
-// evaluated in float32 from rounded magnitudes, 10 * 2^-24 * perm covers
-// gamma_8 * perm of the exact inputs.  The absolute term covers underflow.
-constexpr float kFilterRel = 10.0f * 5.9604644775390625e-8f;
-constexpr float kFilterAbs = 7.888609052210118e-31f;  // 2^-100
-
-// Walk filter.  With w = fl(d_hi x D) and e = fl(a - v), the exact edge value
-// E(v, a) = (a - v) . (d x (v - S)) = (a - v) . (d x (v - Q)) differs from
-// fl(e . w) by at most |e|_1 |d|_inf (20.5 u |D|_inf + 57.2 u^2 R): six
-// roundings per monomial of e.(d_hi x D), the d_lo x D term, and the error of
-// D itself.  The constants below (24 u, 64 u^2) leave room for the rounding of
-// the bound's own evaluation.
-constexpr float kWalkRel = 24.0f * 5.9604644775390625e-8f;
-
-// cos^2 of the angle between the ray and a face normal below which the
-// crossing is recomputed in float64.  With the vertex offset D accurate to a
-// few ulps of |D| (walk_ray), the float32 crossing moves by about c u h / cos
-// (h the face diameter, c ~ 5 from the rounded normal), i.e. 4e-5 h at
-// cos = 1/128; about one segment in ten thousand is that oblique, so the
-// bound on a projection, a sum over some hundred segments, stays near 1e-7
-// of it.
-constexpr float kGrazingCos2 = 1.0f / 16384.0f;
-
-struct Ray {
-  float3 S, P, U, V;
-  float3 d;    // d_hi = fl(P - S)
-  float3 ad;   // |d_hi|
-  double dx64, dy64, dz64;  // P - S (exact in float64)
-  double Mx64, My64, Mz64;  // the ray point at t = 1/2
-  float dn;    // |d| (Euclidean)
-  float gdd;   // |d|^2 / 4096 (grazing test)
-  float kA;    // |d|_inf 24 u        walk filter: K = kA |D|_inf + kB
-  float kB;    // |d|_inf 64 u^2 R, R bounding every coordinate met on this ray
-};
-
 // Per-lane walk statistics (events of one ray; reduced per wave at the end).
 struct LaneStats {
   int steps = 0, zero = 0, fp64 = 0, exact = 0, pert = 0, failed = 0, grazing = 0;
@@ -86,31 +49,6 @@ struct LaneStats {
   __device__ __forceinline__ void add_pert() { pert++; }
   __device__ __forceinline__ void add_failed() { failed++; }
 };
-
-// The ray is carried with d_hi = fl(P - S) for the float32 filters and, in
-// float64, with the exact direction P - S and the point M at t = 1/2 (one
-// float64 rounding), so positions on it near the mesh can be formed to a
-// relative accuracy set by their distance to the mesh features rather than
-// by the distance to the source.
-__device__ __forceinline__ void finish_ray(Ray& r, float mesh_extent) {
-  r.d = f3sub(r.P, r.S);
-  r.dx64 = (double)r.P.x - r.S.x;
-  r.dy64 = (double)r.P.y - r.S.y;
-  r.dz64 = (double)r.P.z - r.S.z;
-  r.Mx64 = r.S.x + 0.5 * r.dx64;
-  r.My64 = r.S.y + 0.5 * r.dy64;
-  r.Mz64 = r.S.z + 0.5 * r.dz64;
-  r.ad = f3abs(r.d);
-  const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
-  r.dn = sqrtf(dd);
-  r.gdd = kGrazingCos2 * dd;  // exact: a power of two
-  const float dinf = fmaxf(r.ad.x, fmaxf(r.ad.y, r.ad.z));
-  float sp = fmaxf(fmaxf(fmaxf(fabsf(r.S.x), fabsf(r.S.y)), fmaxf(fabsf(r.S.z), fabsf(r.P.x))),
-                   fmaxf(fabsf(r.P.y), fabsf(r.P.z)));
-  float R = (fmaxf(sp, mesh_extent) + dinf) * 1.0001f;
-  r.kA = dinf * kWalkRel;
-  r.kB = dinf * (64.0f * 3.552713678800501e-15f * R);  // |d|_inf 64 u^2 R with u = 2^-24
-}
 
 // Pixel ray S -> P(u, v) of one angle's frame.
 __device__ __forceinline__ Ray cone_ray(const GeomView& g, float mesh_extent, int a, int i, int j) {
@@ -164,17 +102,6 @@ __device__ __noinline__ double crossing_s_fp64(float3 S, float3 P, float3 on, fl
 }
 
 
-// D = v - Q for the ray point Q = M + s d, in float64: M, v - M and the
-// fused s d term each carry one float64 rounding of the source-distance
-// scale R, so with the final rounding to float32
-// |D - (v - Q)| <= u |D| + 2^-51 R componentwise, inside the allowance
-// 3.1 u |D| + 28 u^2 R the walk filter below is built on.
-__device__ __forceinline__ float3 offset_from_ray(const Ray& r, double s, float3 v) {
-  return make_float3((float)fma(-s, r.dx64, (double)v.x - r.Mx64), (float)fma(-s, r.dy64, (double)v.y - r.My64),
-                     (float)fma(-s, r.dz64, (double)v.z - r.Mz64));
-}
-
-
 __device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, LaneStats& st) {
   if (fast != 2) return fast;
   int res = slow_edge_sign(r.S, r.P, r.U, r.V, p, q);
@@ -191,34 +118,6 @@ __device__ __forceinline__ int resolve_src(const Src& q, float3 a, float3 b, Lan
   if (res & (kFlagExact << 2)) st.add_exact();
   if (res & (kFlagPerturbed << 2)) st.add_pert();
   return (res & 3) - 1;
-}
-
-// Float32 estimate of sigma(p, q) = (q - p) . w with w = d x (p - S) and
-// W = |d| x |p - S| (the cross-product magnitudes); 2 = uncertain.
-__device__ __forceinline__ int fast_sign(float3 e, float3 w, float3 W) {
-  float E = e.x * w.x + e.y * w.y + e.z * w.z;
-  float B = kFilterRel * (fabsf(e.x) * W.x + fabsf(e.y) * W.y + fabsf(e.z) * W.z) + kFilterAbs;
-  return E > B ? 1 : (E < -B ? -1 : 2);
-}
-
-// The ray leaves through the face (v, a_{k+1}, a_{k+2}) opposite entry slot
-// k (indices mod 3) for which E(v, a_{k+1}) < 0 < E(v, a_{k+2}), the first of
-// k = 2, 0, 1 that qualifies.  When the three signs are certain (nonzero)
-// this is a table on n = neg0 | neg1 << 1 | neg2 << 2, two bits per entry;
-// 3 = none (all three signs equal: the walk has failed).
-constexpr unsigned kExitFace = 0xD90Bu;
-
-__device__ __forceinline__ int walk_sign(float3 e, float3 w, float K) {
-  float E = e.x * w.x + e.y * w.y + e.z * w.z;
-  float B = (fabsf(e.x) + fabsf(e.y) + fabsf(e.z)) * K + kFilterAbs;
-  return E > B ? 1 : (E < -B ? -1 : 2);
-}
-
-__device__ __forceinline__ void cross_pair(const Ray& r, float3 p, float3& w, float3& W) {
-  float3 pv = f3sub(p, r.S);
-  w = f3cross(r.d, pv);
-  float3 apv = f3abs(pv);
-  W = make_float3(r.ad.y * apv.z + r.ad.z * apv.y, r.ad.z * apv.x + r.ad.x * apv.z, r.ad.x * apv.y + r.ad.y * apv.x);
 }
 
 // Exact entry test for boundary face b (slots in outward order).
@@ -468,29 +367,20 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     return false;
   }
   const float3 v = w.v;
-  float3 D = offset_from_ray(r, w.s_in, v);
-  float3 wv = f3cross(r.d, D);
-  float K = fmaf(fmaxf(fabsf(D.x), fmaxf(fabsf(D.y), fabsf(D.z))), r.kA, r.kB);
-  float3 e0 = f3sub(w.a0, v), e1 = f3sub(w.a1, v), e2 = f3sub(w.a2, v);
-  const float E0 = f3dot(e0, wv), E1 = f3dot(e1, wv), E2 = f3dot(e2, wv);
-  const float l0 = fabsf(e0.x) + fabsf(e0.y) + fabsf(e0.z);
-  const float l1 = fabsf(e1.x) + fabsf(e1.y) + fabsf(e1.z);
-  const float l2 = fabsf(e2.x) + fabsf(e2.y) + fabsf(e2.z);
+  StepEdges g;
+  step_edges(r, w.s_in, v, w.a0, w.a1, w.a2, g);
+  const float3 D = g.D, e0 = g.e0, e1 = g.e1, e2 = g.e2;
   // One bound from the longest edge settles all three signs in the common
   // case; otherwise each edge gets its own bound before any float64 work.
-  int k;
-  if (fminf(fabsf(E0), fminf(fabsf(E1), fabsf(E2))) > fmaf(fmaxf(l0, fmaxf(l1, l2)), K, kFilterAbs)) {
-    const unsigned n = (__float_as_uint(E0) >> 31) | ((__float_as_uint(E1) >> 31) << 1) |
-                       ((__float_as_uint(E2) >> 31) << 2);
-    k = (int)((kExitFace >> (2 * n)) & 3u);
-  } else {
-    const float m0 = fabsf(E0) - fmaf(l0, K, kFilterAbs);
-    const float m1 = fabsf(E1) - fmaf(l1, K, kFilterAbs);
-    const float m2 = fabsf(E2) - fmaf(l2, K, kFilterAbs);
-    const int s0 = m0 > 0.f ? (E0 > 0.f ? 1 : -1) : resolve_src(q, v, w.a0, st);
-    const int s1 = m1 > 0.f ? (E1 > 0.f ? 1 : -1) : resolve_src(q, v, w.a1, st);
-    const int s2 = m2 > 0.f ? (E2 > 0.f ? 1 : -1) : resolve_src(q, v, w.a2, st);
-    k = (s0 < 0 && s1 > 0) ? 2 : (s1 < 0 && s2 > 0) ? 0 : (s2 < 0 && s0 > 0) ? 1 : 3;
+  int k = step_exit_common(g);
+  if (k < 0) {
+    int s0 = step_edge_certified(g.E0, g.l0, g.K);
+    int s1 = step_edge_certified(g.E1, g.l1, g.K);
+    int s2 = step_edge_certified(g.E2, g.l2, g.K);
+    if (s0 == 0) s0 = resolve_src(q, v, w.a0, st);
+    if (s1 == 0) s1 = resolve_src(q, v, w.a1, st);
+    if (s2 == 0) s2 = resolve_src(q, v, w.a2, st);
+    k = exit_slot(s0, s1, s2);
   }
   if (k == 3) {
     st.add_failed();
