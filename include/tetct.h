@@ -138,37 +138,69 @@ tct_status tct_mesh_boundary(const tct_mesh* m, float* xyz, int32_t* owner);
 tct_status tct_mesh_rstar(const tct_mesh* m, int32_t* nnodes, int32_t* nlist, int32_t* height, float* box,
                           int32_t* link, int32_t* list);
 
-/* Sizes: node count, tetrahedron count, boundary faces, device bytes held. Any pointer may be NULL. */
+/* Sizes of the element graph (Section II-B: nodes, elements and the boundary
+ * elements the entry search starts from): node count, tetrahedron count,
+ * boundary faces, device bytes held.  Any pointer may be NULL; TCT_E_ARG for a
+ * null mesh. */
 tct_status tct_mesh_counts(const tct_mesh* m, int32_t* nv, int32_t* nt, int32_t* nboundary, int64_t* device_bytes);
 
-/* host int32 [nt]: user id of each internal tetrahedron. */
+/* The element order of the internal layout (not in the paper: the library
+ * reorders the elements of Section II-B along a Morton curve so that
+ * neighbours across faces sit close in memory).
+ *   internal_to_user  host int32 [nt], caller-owned: user id of each internal tetrahedron
+ * TCT_E_ARG for a null mesh or output. */
 tct_status tct_mesh_permutation(const tct_mesh* m, int32_t* internal_to_user);
 
-/* host int32 [nt][4]: neighbour (user ids, -1 boundary) across face k of each
- * user tetrahedron, with faces numbered by the user's vertex order. */
+/* The ordered neighbour list of Section II-B (Fig. 1) as the library built or
+ * checked it: host int32 [nt][4], caller-owned, the neighbour (user ids, -1 on
+ * the boundary) across face k of each user tetrahedron, faces numbered by the
+ * user's vertex order.  TCT_E_ARG for a null mesh or output. */
 tct_status tct_mesh_neighbors(const tct_mesh* m, int32_t* nbrs);
 
-/* device float [nt]: x_internal[i] = x_user[perm[i]]  /  x_user[perm[i]] = x_internal[i]. */
+/* Per-element values (x of Eq. 2, xhat of Eq. 3) between the user's element
+ * order and the internal one: device float [nt] each, caller-owned, not
+ * aliased; x_internal[i] = x_user[perm[i]]  /  x_user[perm[i]] = x_internal[i]
+ * with perm from tct_mesh_permutation.  Asynchronous on s; TCT_E_ARG for null
+ * pointers or a host-only mesh. */
 tct_status tct_mesh_to_internal(const tct_mesh* m, const float* x_user, float* x_internal, tct_stream s);
 tct_status tct_mesh_to_user(const tct_mesh* m, const float* x_internal, float* x_user, tct_stream s);
 
-/* Counters since the last reset; synchronises the device.  Returns TCT_E_WALK
- * when failed > 0 (the counters are still written). */
+/* Walk counters since the last reset (see tct_stats).  The paper requires that
+ * no ray halts or loops inside the mesh (Section II-C, the failure cases of
+ * Fig. 3); `failed` counts rays that did, so a caller can detect them.
+ *   out    host, filled (may be NULL)
+ *   reset  non-zero: zero the counters after reading
+ * Synchronises the device.  Returns TCT_E_WALK when failed > 0 (the counters
+ * are still written); TCT_E_ARG for a null or host-only mesh. */
 tct_status tct_stats_read(const tct_mesh* m, tct_stats* out, int reset);
 
+/* Frees the mesh and its device memory (NULL is a no-op).  No call using the
+ * mesh may still be running on any stream. */
 void tct_mesh_destroy(tct_mesh* m);
 
 /* ---------------------------------------------------------------- geometry */
 
-/* angles_rad host double [na].  Copies to the device. */
+/* Circular cone-beam geometry with the given source angles (Section III-A:
+ * cone beam on a circular trajectory; the rays of Algorithm 2 run from the
+ * source R1 to each pixel centre R2).
+ *   cone        host, see tct_cone
+ *   angles_rad  host double [na], any values (the experiments use equidistant ones)
+ *   device      HIP device ordinal; frames and pixel tables are copied there
+ * The host arrays are copied; the handle owns its device memory until
+ * tct_geom_destroy.  TCT_E_ARG unless na, nu, nv >= 1 and 0 < dso < dsd, or
+ * for 2^40 rays or more; TCT_E_HIP / TCT_E_NOMEM when the upload fails.  Whether a mesh lies between source and detector is
+ * checked when both are used together (TCT_E_GEOM). */
 tct_status tct_geom_create(const tct_cone* cone, const double* angles_rad, int32_t na, int device, tct_geom** out);
 
-/* Number of rays na * nv * nu. */
+/* Number of rays na * nv * nu (one per pixel and angle, Section III-A); 0 for NULL. */
 int64_t tct_geom_nrays(const tct_geom* g);
 
-/* host float: S, D, U, V [na][3] and the pixel-centre tables u [nu], v [nv], as used by the kernels. */
+/* The float32 frames the kernels build rays from (Section III-A geometry, the
+ * rounding rule of tct_cone): host float S, D, U, V [na][3] and the pixel-centre
+ * tables u [nu], v [nv], caller-owned; any pointer may be NULL. */
 tct_status tct_geom_frame(const tct_geom* g, float* S, float* D, float* U, float* V, float* u, float* v);
 
+/* Frees the geometry and its device memory (NULL is a no-op). */
 void tct_geom_destroy(tct_geom* g);
 
 /* ---------------------------------------------------------------- operators */
@@ -274,7 +306,10 @@ typedef struct {
 tct_status tct_forward_paper(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
                              int precision, tct_paper_stats* stats, tct_stream s);
 
-/* Visited tetrahedra of selected rays, zero-length passages included, in CSR form.
+/* Visited tetrahedra of selected rays, zero-length passages included, in CSR
+ * form: row j of the system matrix (Section II-A, Eq. 1: a_ij = length of ray j
+ * inside tetrahedron i) in visiting order, the sequence Algorithm 2 walks
+ * (zero-length passages through edges and vertices, Fig. 3, included).
  *   ray_ids  device int64 [nrays]
  *   offsets  device int64 [nrays + 1]   written: ray k owns [offsets[k], offsets[k+1])
  *   tets     device int32 [cap]          user ids
@@ -284,7 +319,8 @@ tct_status tct_forward_paper(const tct_mesh* m, const tct_geom* g, const float* 
 tct_status tct_trace(const tct_mesh* m, const tct_geom* g, const int64_t* ray_ids, int32_t nrays, int64_t* offsets,
                      int32_t* tets, float* lengths, int64_t cap, int64_t* needed, tct_stream s);
 
-/* Same for caller-given rays: device float [n][3] arrays S, P (endpoints) and
+/* Same for caller-given rays (Algorithm 2's R1 = S, R2 = P, not tied to a
+ * detector): device float [n][3] arrays S, P (endpoints) and
  * U, V (tie-breaking axes; {P - S, U, V} must be a basis, else the ray is
  * counted as failed and gets an empty path). */
 tct_status tct_trace_rays(const tct_mesh* m, const float* S, const float* P, const float* U, const float* V,

@@ -38,30 +38,52 @@ def gradient(A, x, b) -> np.ndarray:
     return A.T @ (A @ x - b)
 
 
-def cgls(A, b, iters: int, x0=None):
+def cgls(A, b, iters: int, x0=None, precision: int = 64):
     """Conjugate gradients on A^T A x = A^T b (Hestenes-Stiefel form for least squares).
 
-    Returns (x, rr, xs) with rr[k] = ||b - A x_k||^2 for k = 0..iters and xs the iterates.
+    precision=32 runs the same recurrence with float32 vectors: the matrix
+    entries, b and every vector are float32, each product with A or A^T is
+    accumulated in float64 and rounded to float32 (as a float32 projector
+    returns it), and the inner products are float64 scalars.
+
+    Returns (x, rr, xs) with rr[k] = ||b - A x_k||^2 (float64) for k = 0..iters
+    and xs the iterates.
     """
-    x = np.zeros(A.shape[1]) if x0 is None else np.array(x0, np.float64)
-    r = b - A @ x
-    s = A.T @ r
+    if precision == 64:
+        vec = np.float64
+        Am = A
+    elif precision == 32:
+        vec = np.float32
+        Am = sp.csr_matrix(A, dtype=np.float32).astype(np.float64)
+    else:
+        raise ValueError("precision must be 32 or 64")
+
+    def mv(M, v):
+        return (M @ v.astype(np.float64)).astype(vec)
+
+    def dot(a, c):
+        return float(np.dot(a.astype(np.float64), c.astype(np.float64)))
+
+    b = np.asarray(b).astype(vec)
+    x = np.zeros(A.shape[1], vec) if x0 is None else np.array(x0, vec)
+    r = (b - mv(Am, x)).astype(vec)
+    s = mv(Am.T, r)
     p = s.copy()
-    gamma = float(s @ s)
-    rr = [float(r @ r)]
+    gamma = dot(s, s)
+    rr = [dot(r, r)]
     xs = [x.copy()]
     for _ in range(iters):
-        q = A @ p
-        delta = float(q @ q)
+        q = mv(Am, p)
+        delta = dot(q, q)
         alpha = gamma / delta if delta != 0 else 0.0
-        x = x + alpha * p
-        r = r - alpha * q
-        s = A.T @ r
-        gamma_new = float(s @ s)
+        x = (x + vec(alpha) * p).astype(vec)
+        r = (r - vec(alpha) * q).astype(vec)
+        s = mv(Am.T, r)
+        gamma_new = dot(s, s)
         beta = gamma_new / gamma if gamma != 0 else 0.0
-        p = s + beta * p
+        p = (s + vec(beta) * p).astype(vec)
         gamma = gamma_new
-        rr.append(float(r @ r))
+        rr.append(dot(r, r))
         xs.append(x.copy())
     return x, np.array(rr), xs
 

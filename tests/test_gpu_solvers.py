@@ -107,15 +107,19 @@ def test_cgls_history_matches_oracle():
     iters = 50
     x, rr = S.tct.cgls(S.P, S.b_t, iters)
     _, rr_ref, _ = osolv.cgls(S.A, S.b, iters)
+    _, rr32, _ = osolv.cgls(S.A, S.b, iters, precision=32)
     rel = np.abs(rr - rr_ref) / rr_ref
     # Identical recurrences agree closely until float32 rounding erodes the
-    # conjugacy of the search directions; the same CGLS run in float32 on the
-    # CPU departs from float64 by O(1) after ~15 iterations on this system.
-    # Beyond k = 10 the GPU must keep converging: monotone, within 5x of the
-    # float64 residual, and below 1e-5 of the initial residual at k = 50.
+    # conjugacy of the search directions; after that the float64 history is
+    # no longer the reference: the same recurrence with float32 vectors on
+    # the CPU departs from it by up to a factor ~4 on this system (pinned in
+    # test_oracle_solvers.py), and the GPU, another float32 evaluation of
+    # it, must follow that float32 history within a factor 1.5.
+    print("GPU / float64:", np.round((rr / rr_ref)[::5], 3))
+    print("GPU / float32 CPU:", np.round((rr / rr32)[::5], 3))
     assert np.all(rel[:11] <= 1e-4), rel[:11]
-    ratio = rr / rr_ref
-    assert np.all((ratio > 0.2) & (ratio < 5.0)), ratio
+    ratio32 = rr / rr32
+    assert np.all((ratio32 > 1 / 1.5) & (ratio32 < 1.5)), ratio32
     assert np.all(np.diff(rr) <= 1e-6 * rr[0])
     assert rr[-1] <= 1e-5 * rr[0]
 

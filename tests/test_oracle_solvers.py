@@ -110,3 +110,38 @@ def test_os_sart_converges_on_consistent_system(small):
     xs, rrs = solvers.sirt(A, b, 5)
     x1, rr1 = solvers.os_sart(A, b, 5, [np.arange(o.nrays)])
     assert np.allclose(x1, xs, rtol=1e-12, atol=1e-14) and np.allclose(rr1, rrs, rtol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def cfg0_system():
+    w = synth.config(3)
+    o = oracle.Oracle(w.verts, w.tets, w.cone, w.angles)
+    A = solvers.system_matrix(o)
+    b = A @ synth.uniform_random(o.nt, w.meta["target_seed"]).astype(np.float64)
+    return A, b
+
+
+def test_cgls_float32_departs_from_float64(cfg0_system):
+    """The CGLS recurrence with float32 vectors (the precision of the GPU
+    solver) follows float64 CGLS to 1e-6 for ten iterations on the Kuhn 8^3 /
+    64^2 x 16 system, then departs by tens of percent and more: rounding
+    erodes the conjugacy of the search directions.  The departure is a
+    property of float32 arithmetic, not of one rounding order: the same
+    recurrence on the rows in another order departs the same way, while
+    float64 CGLS is order-independent over the same early span."""
+    A, b = cfg0_system
+    iters = 50
+    _, rr64, _ = solvers.cgls(A, b, iters)
+    _, rr32, _ = solvers.cgls(A, b, iters, precision=32)
+    ratio = rr32 / rr64
+    print("float32 / float64 residuals every 5 iterations:", np.round(ratio[::5], 3))
+    assert np.all(np.abs(ratio[:11] - 1) <= 1e-6), ratio[:11]
+    assert np.max(np.abs(ratio[15:] - 1)) > 0.2
+    assert np.all(np.diff(rr32) <= 0)  # still a descent method
+    perm = np.random.default_rng(8).permutation(A.shape[0])
+    _, rr32p, _ = solvers.cgls(A[perm], b[perm], iters, precision=32)
+    spread = np.abs(rr32p / rr32 - 1)
+    print(f"float32, rows permuted: largest relative change {spread.max():.3f}")
+    assert np.all(spread <= 0.25)
+    _, rr64p, _ = solvers.cgls(A[perm], b[perm], iters)
+    assert np.all(np.abs(rr64p[:16] / rr64[:16] - 1) <= 1e-6)
