@@ -41,9 +41,13 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    L = C.CDLL(_LIB)
+    override = os.environ.get("TCT_ORACLE_LIB")  # an instrumented build (sanitizer tests)
+    if override:
+        L = C.CDLL(override)
+    else:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
     L.orc_last_error.restype = C.c_char_p
     L.orc_exact_calls.restype = C.c_longlong
     L.orc_last_stats.argtypes = [_i64p]

@@ -10,7 +10,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtetct.so")
+# TCT_LIB_PATH selects another build of the same library (the sanitizer
+# tests load an instrumented one); by default the in-tree build.
+LIB_PATH = os.environ.get("TCT_LIB_PATH") or os.path.join(HERE, "libtetct.so")
 
 STATUS = {
     0: "TCT_OK",

@@ -629,3 +629,34 @@ def test_full_size_sampled_backprojection_against_oracle(name):
         print(f"{name} sampled {mode} backprojection: values {ref}, err/tol {err / tol}")
         assert np.all(err <= tol), (mode, got, ref, tol)
     check_stats(c.mesh)
+
+
+def test_walk_failure_is_counted_and_reported():
+    """Section II-C requires that a ray never halts unnoticed.  A custom ray
+    whose tie-breaking axes do not span space together with its direction
+    cannot be walked under the perturbation rule, so the library counts it
+    as failed (and gives it an empty path) instead of walking it:
+    tct_stats_read then returns TCT_E_WALK with the counters filled, and a
+    reset clears them."""
+    import ctypes
+
+    from paper_1908_06909_amd._lib import lib, tct_stats
+
+    tct = _gpu()
+    X = synth.kuhn_nodes(2)
+    verts, tets = synth.kuhn_mesh(X, X, X)
+    m = tct.TetMesh(verts, tets, device=DEV)
+    ex, ey, ez = np.eye(3, dtype=f32)
+    S = np.array([[4, 0.1, 0.2], [4, 0.1, 0.2]], f32)
+    P = np.array([[-4, 0.1, 0.2], [-4, 0.1, 0.2]], f32)
+    U = np.array([ex, ey], f32)  # ray 0: U parallel to P - S
+    V = np.array([ey, ez], f32)
+    m.stats(reset=True)
+    (t0, _), (t1, l1) = tct.trace_rays(m, S, P, U, V)
+    assert len(t0) == 0 and len(t1) > 0
+    assert abs(float(l1.sum()) - 1.0) <= 1e-6
+    st = tct_stats()
+    assert lib().tct_stats_read(m.handle, ctypes.byref(st), 1) == -9
+    assert st.failed == 1 and st.rays == 2
+    assert lib().tct_stats_read(m.handle, ctypes.byref(st), 0) == 0
+    assert st.failed == 0

@@ -115,3 +115,56 @@ def test_morton_reorder_keeps_neighbours_local():
     gap_user = np.abs(src[ok] - dst[ok])
     # more neighbours within a 64-element window (a few cache lines of records)
     assert (gap_internal < 64).mean() > (gap_user < 64).mean()
+
+
+@pytest.mark.parametrize("kind", ["self_loop", "out_of_range", "negative_id", "boundary_claimed_interior",
+                                  "interior_claimed_boundary", "one_sided"])
+def test_neighbour_table_rejections(kind):
+    """A caller-given neighbour table (Section II-B's ordered neighbour list)
+    that contradicts the connectivity is rejected through the C ABI with
+    TCT_E_MESH_NONMANIFOLD: a walk over it could loop or leave the mesh
+    through an interior face (the failures Section II-C rules out)."""
+    verts, tets = _kuhn(2)
+    nb = TetMesh(verts, tets, host_only=True).neighbors()
+    bad = nb.copy()
+    t_in, k_in = map(int, np.argwhere(nb >= 0)[0])  # an interior face
+    t_bd, k_bd = map(int, np.argwhere(nb < 0)[0])  # a boundary face
+    if kind == "self_loop":
+        bad[t_in, k_in] = t_in
+    elif kind == "out_of_range":
+        bad[t_in, k_in] = len(tets) + 5
+    elif kind == "negative_id":
+        bad[t_in, k_in] = -7
+    elif kind == "boundary_claimed_interior":
+        bad[t_bd, k_bd] = (t_bd + 1) % len(tets)
+    elif kind == "interior_claimed_boundary":
+        bad[t_in, k_in] = -1
+    elif kind == "one_sided":
+        # t's neighbour list names u, but u's list does not name t back
+        u = int(nb[t_in, k_in])
+        back = int(np.flatnonzero(nb[u] == t_in)[0])
+        bad[u, back] = -1
+    h = C.c_void_p()
+    v = np.ascontiguousarray(verts, np.float32)
+    t = np.ascontiguousarray(tets, np.int32)
+    b = np.ascontiguousarray(bad, np.int32)
+    st = _lib.lib().tct_mesh_create(v.ctypes.data, len(v), t.ctypes.data, len(t), b.ctypes.data,
+                                    _lib.TCT_MESH_HOST_ONLY, 0, C.byref(h))
+    assert st == -3, (kind, st)
+    assert not h.value
+    assert b"neighbour" in _lib.lib().tct_last_error()
+
+
+def test_null_arguments_are_rejected():
+    L = _lib.lib()
+    h = C.c_void_p()
+    verts, tets = _kuhn(1)
+    v = np.ascontiguousarray(verts, np.float32)
+    t = np.ascontiguousarray(tets, np.int32)
+    assert L.tct_mesh_create(None, len(v), t.ctypes.data, len(t), None, _lib.TCT_MESH_HOST_ONLY, 0, C.byref(h)) == -1
+    assert L.tct_mesh_create(v.ctypes.data, len(v), None, len(t), None, _lib.TCT_MESH_HOST_ONLY, 0, C.byref(h)) == -1
+    assert L.tct_mesh_create(v.ctypes.data, len(v), t.ctypes.data, len(t), None, _lib.TCT_MESH_HOST_ONLY, 0,
+                             None) == -1
+    assert L.tct_mesh_counts(None, None, None, None, None) == -1
+    assert L.tct_stats_read(None, None, 0) == -1
+    assert L.tct_backproject(None, None, None, None, 0, 0, None, None) == -1
