@@ -1041,6 +1041,70 @@ int orc_backproject_ext(void* h, const double* cone, const double* angles, int n
   return status.load();
 }
 
+// One pass over the listed rays that gives a parity test both the
+// oracle's values and the quantities its error bounds are made of.
+// x and w are per tetrahedron (w: a weight such as the element size), y per
+// listed ray.  Per listed ray i: b[i] = sum_k L_k x_{t_k} (Eq. 2),
+// babs[i] = sum_k L_k |x_{t_k}|, chord[i] = sum_k L_k, wx[i] = the largest
+// w_t |x_t| over the tetrahedra its walk visits.  Per tetrahedron t:
+// xhat[t] = sum_j a_tj y_j (Eq. 3), xabs[t] = sum_j a_tj |y_j|, supp[t] = sum
+// of |y_j| over the rays whose walk visits t (zero-length passages
+// included), suppc[t] = the same sum weighted by each ray's chord, cnt[t] =
+// the number of those visits.  Per-thread float64 partials, added in thread
+// order.
+int orc_check_pass(void* h, const double* cone, const double* angles, int na, const float* x, const double* w,
+                   const float* y, const long long* ids, long long n, double* b, double* babs, double* chord, double* wx,
+                   double* xhat, double* xabs, double* supp, double* suppc, double* cnt, int nthreads) {
+  const Mesh& m = *(const Mesh*)h;
+  Frame f = make_frame(cone_from(cone), angles, na);
+  int nth = nthreads_of(nthreads);
+  const size_t nt = (size_t)m.nt;
+  std::vector<std::vector<double>> part(nth, std::vector<double>(5 * nt, 0.0));
+  std::vector<WalkStats> ws(nth);
+  std::atomic<int> status{OK};
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nth)
+  for (long long i = 0; i < n; ++i) {
+    std::vector<Visit> path;
+    Ray r = make_ray(f, ids[i]);
+    int tid = thread_id();
+    int st = walk(m, r, &path, &ws[tid]);
+    if (st != OK) status = st;
+    Neumaier sb, sa, sc;
+    double mx = 0.0;
+    for (const auto& v : path) {
+      const double xv = (double)x[v.tet];
+      sb.add(v.len * xv);
+      sa.add(v.len * std::fabs(xv));
+      sc.add(v.len);
+      mx = std::max(mx, w[v.tet] * std::fabs(xv));
+    }
+    b[i] = sb.value();
+    babs[i] = sa.value();
+    chord[i] = sc.value();
+    wx[i] = mx;
+    const double yv = (double)y[i], ya = std::fabs(yv), c = chord[i];
+    double* p = part[tid].data();
+    for (const auto& v : path) {
+      double* q = p + 5 * (size_t)v.tet;
+      q[0] += v.len * yv;
+      q[1] += v.len * ya;
+      q[2] += ya;
+      q[3] += c * ya;
+      q[4] += 1.0;
+    }
+  }
+  double* outs[5] = {xhat, xabs, supp, suppc, cnt};
+  for (size_t t = 0; t < nt; ++t)
+    for (int c = 0; c < 5; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < nth; ++k) s += part[k][5 * t + c];
+      outs[c][t] = s;
+    }
+  g_last = WalkStats();
+  for (auto& x : ws) g_last.add(x);
+  return status.load();
+}
+
 namespace {
 int trace_common(const Mesh& m, const std::vector<Ray>& rays, long long* offsets, int* tets, double* lens,
                  long long cap) {

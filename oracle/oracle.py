@@ -74,6 +74,8 @@ def lib():
                                   C.c_int]
     L.orc_backproject_ext.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f32p, C.c_void_p, C.c_longlong,
                                       _f64p, _f64p, _f64p, C.c_int]
+    L.orc_check_pass.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f32p, _f64p, _f32p, _i64p, C.c_longlong] + \
+        [_f64p] * 9 + [C.c_int]
     L.orc_trace.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _i64p, C.c_longlong, _i64p, _i32p, _f64p,
                             C.c_longlong]
     L.orc_trace_rays.argtypes = [C.c_void_p, _f32p, _f32p, _f32p, _f32p, C.c_longlong, _i64p, _i32p, _f64p,
@@ -277,6 +279,27 @@ class Oracle:
                                        None if ids_a is None else ids_a.ctypes.data, n, *out, self.nthreads)
         self._check(st)
         return tuple(out)
+
+    def check_pass(self, x, w, y, ids):
+        """One walk of the listed rays giving values and error-bound terms:
+        per ray b (Eq. 2), babs = sum a|x|, chord, wx = max of w_t |x_t| over
+        the visited tetrahedra; per tetrahedron xhat (Eq. 3), xabs = sum a|y|,
+        supp = sum of |y_j| over the rays that visit it (zero-length passages
+        included), suppc = the same weighted by chord_j, cnt = the number of
+        visits.  y is given per listed ray."""
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        n = len(ids)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float32).ravel()
+        assert len(x) == self.nt and len(w) == self.nt and len(y) == n
+        per_ray = [np.zeros(n, np.float64) for _ in range(4)]
+        per_tet = [np.zeros(self.nt, np.float64) for _ in range(5)]
+        st = lib().orc_check_pass(self.mesh._h, self._cone, self.angles, self.na, x, w, y, ids, n, *per_ray,
+                                  *per_tet, self.nthreads)
+        self._check(st)
+        names = ("b", "babs", "chord", "wx", "xhat", "xabs", "supp", "suppc", "cnt")
+        return dict(zip(names, per_ray + per_tet))
 
     def trace(self, ids):
         """List of (tets int32, lengths float64) per listed ray."""

@@ -111,17 +111,14 @@ def test_coplanar_source_entry_and_forward_match_oracle():
     ids = np.arange(orc.nrays)
     _, owner = mesh.boundary()
     trace = orc.trace(ids)
-    tv = np.zeros(len(ids))
     for rid, (tt, _) in enumerate(trace):
         if e[rid] < 0:
             assert len(tt) == 0, rid
         else:
             assert len(tt) > 0 and owner[e[rid]] == tt[0], rid
-            xs = np.concatenate([[0.0], w.x[tt].astype(np.float64), [0.0]])
-            tv[rid] = np.abs(np.diff(xs)).sum()
-    ref = orc.forward(w.x, ids)
-    S, Pp, _, _ = orc.rays(ids)
-    tol = 1e-5 * orc.forward(np.abs(w.x), ids) + 1e-5 * np.linalg.norm(Pp.astype(np.float64) - S, axis=1) / 64 * tv
+    from parity_bars import element_size, forward_reference
+
+    ref, tol = forward_reference(orc, w.x, element_size(w.verts, w.tets, orc.mesh.tables()[1]), ids)
     err = np.abs(got - ref)
     print(f"coplanar: {int((e >= 0).sum())} rays enter; {st['perturbed_ties']} perturbed ties; "
           f"worst err/tol {float(np.max(err / np.maximum(tol, 1e-300))):.3f}")

@@ -367,3 +367,38 @@ def test_walk_invariants_jittered():
             assert -1 in N[tt[0]] and -1 in N[tt[-1]]
     st = oracle.oracle.last_stats()
     assert st.failed == 0 and st.multi_entry == 0
+
+
+def test_check_pass_terms_match_traces():
+    """The one-pass bound terms the GPU tests use equal the same quantities
+    assembled in numpy from the oracle's traces (a jittered mesh with rays
+    that miss and rays that clip the hull; the sums over visits include the
+    zero-length passages)."""
+    w = synth.jittered_kuhn(3, 5, 13, 13, 11, 3)
+    w.cone = synth.Cone(4.0, 8.0, 13, 11, 0.2, 0.23, 0.01, -0.02)  # wider than the mesh's shadow
+    o = oracle.Oracle(w.verts, w.tets, w.cone, w.angles)
+    rng = np.random.default_rng(5)
+    ids = np.arange(o.nrays)
+    y = rng.uniform(-1, 1, o.nrays).astype(np.float32)
+    x = rng.uniform(-1, 1, o.nt).astype(np.float32)
+    wt = rng.uniform(0.5, 2.0, o.nt)
+    r = o.check_pass(x, wt, y, ids)
+    b = np.zeros(o.nrays)
+    babs = np.zeros(o.nrays)
+    chord = np.zeros(o.nrays)
+    wx = np.zeros(o.nrays)
+    xhat, xabs, supp, suppc, cnt = (np.zeros(o.nt) for _ in range(5))
+    for j, (tt, ll) in enumerate(o.trace(ids)):
+        b[j] = np.sum(ll * x[tt])
+        babs[j] = np.sum(ll * np.abs(x[tt]))
+        chord[j] = ll.sum()
+        wx[j] = np.max(wt[tt] * np.abs(x[tt])) if len(tt) else 0.0
+        np.add.at(xhat, tt, ll * float(y[j]))
+        np.add.at(xabs, tt, ll * abs(float(y[j])))
+        np.add.at(supp, tt, abs(float(y[j])))
+        np.add.at(suppc, tt, chord[j] * abs(float(y[j])))
+        np.add.at(cnt, tt, 1)
+    assert (chord == 0).sum() > 0 and (chord > 0).sum() > 0
+    for k, v in (("b", b), ("babs", babs), ("chord", chord), ("wx", wx), ("xhat", xhat), ("xabs", xabs),
+                 ("supp", supp), ("suppc", suppc), ("cnt", cnt)):
+        assert np.allclose(r[k], v, rtol=1e-12, atol=1e-13), k
