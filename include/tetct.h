@@ -267,6 +267,24 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
 tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
                            int accumulate, const int32_t* entry, tct_stream s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * reproducible scatter of tct_backproject(mode = TCT_BP_FIXED), same arguments
+ * and the same bits, without any allocation.  Its scratch (8 bytes per
+ * tetrahedron plus 256) is a static device array sized for
+ * TCT_NOALLOC_MAX_TETS tetrahedra (32 MiB), held by each GPU the library runs
+ * on until the process ends; the first call on a device looks its address
+ * up.  Every call on one GPU shares that array and clears what it needs at
+ * its start, so calls that overlap in time on one GPU (several streams or
+ * threads) race and give wrong results.  The caller still passes inputs and
+ * outputs.
+ *   Errors: TCT_E_ARG for null arguments, a mesh/geometry device mismatch or a
+ *   mesh of more than TCT_NOALLOC_MAX_TETS tetrahedra; TCT_E_HIP when the
+ *   scratch address cannot be looked up or a launch fails.  Asynchronous on s. */
+#define TCT_NOALLOC_MAX_TETS 4194304
+tct_status tct_backproject_fixed_noalloc(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat,
+                                         int accumulate, const int32_t* entry, tct_stream s);
+
 /* Launch options: the angles [a0, a0 + na) to process (projection arrays keep
  * their full [na_total][nv][nu] layout; other angles are not touched) and the
  * wavefront pixel tile width tile_u in {4, 8, 16, 32, 64} (tile height

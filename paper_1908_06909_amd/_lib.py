@@ -36,6 +36,7 @@ TCT_BP_GATHER = 1
 TCT_BP_ATOMIC_DIRECT = 2
 TCT_BP_SHADOW = 3
 TCT_BP_FIXED = 4
+TCT_NOALLOC_MAX_TETS = 4194304
 TCT_DOT_WORKSPACE = 512
 TCT_VECSET_DOT_WORKSPACE = 256
 
@@ -104,6 +105,7 @@ _SIGS = {
     "tct_forward_range": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "tct_forward_paper": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.POINTER(tct_paper_stats), _P]),
     "tct_backproject_range": (C.c_int, [_P, _P, _P, _P, C.c_int, C.c_int, _P, _P, _P]),
+    "tct_backproject_fixed_noalloc": (C.c_int, [_P, _P, _P, _P, C.c_int, _P, _P]),
     "tct_vecset_create": (C.c_int, [C.c_int32, _P, _P, C.c_int, C.POINTER(_P)]),
     "tct_vecset_destroy": (None, [_P]),
     "tct_vecset_dot": (C.c_int, [_P, _P, _P, _P, _P]),

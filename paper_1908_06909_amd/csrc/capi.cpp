@@ -381,6 +381,18 @@ tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* pr
                             (hipStream_t)s);
 }
 
+tct_status tct_backproject_fixed_noalloc(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat,
+                                         int accumulate, const int32_t* entry, tct_stream s) {
+  tct_status st = check_pair(m, g);
+  if (st != TCT_OK) return st;
+  if (!proj || !xhat) {
+    set_error("tct_backproject_fixed_noalloc: null input or output");
+    return TCT_E_ARG;
+  }
+  DeviceGuard dg(m->device);
+  return backproject_fixed_noalloc(m, g, proj, xhat, accumulate, entry, default_tile_u(), (hipStream_t)s);
+}
+
 tct_status tct_forward_paper(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
                              int precision, tct_paper_stats* stats, tct_stream s) {
   tct_status st = check_pair(m, g);

@@ -39,6 +39,8 @@ tct_status launch_permute(const float* in, float* out, const int32_t* perm, int 
 
 tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
                              const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s);
+tct_status backproject_fixed_noalloc(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat,
+                                     int accumulate, const int32_t* entry, int tile_u, hipStream_t s);
 
 tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
                               const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s);

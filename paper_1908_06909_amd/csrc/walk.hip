@@ -28,6 +28,7 @@
 // estimated in float32 as (q - p) . ((P - S) x (p - S)) with a certified
 // error bound; the rare uncertain cases go to a non-inlined float64 /
 // exact-expansion routine (exact.h).
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -1086,9 +1087,13 @@ tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float*
 // and K = 62 - ceil(log2(rays)), so each term is below 2^K in magnitude and
 // no tetrahedron's sum of at most `rays` terms can reach 2^62.  The block
 // tables and the global sums then add integers, exactly, in any order.
-tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
-                             const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s) {
-  if (m->nt <= 0) return TCT_OK;
+// Scratch layout of the reproducible scatter: [max |y| bits, scale exponent,
+// pad to 256 B][nt int64 sums].
+static size_t fixed_scratch_bytes(int nt) { return 256 + 8 * (size_t)nt; }
+
+static tct_status backproject_fixed_in(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat,
+                                       int accumulate, const int32_t* entry, int tile_u, int a_begin, int a_count,
+                                       hipStream_t s, char* scratch) {
   const int64_t per_angle = (int64_t)g->cone.nu * g->cone.nv;
   const int64_t nrays = per_angle * a_count;
   if (nrays <= 0) return accumulate ? TCT_OK : launch_fill(xhat, m->nt, 0.f, s);
@@ -1111,10 +1116,7 @@ tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* 
   int bits = 1;
   while (bits < 62 && ((int64_t)1 << bits) < nrays) ++bits;
   const int K = 62 - bits;
-  // Scratch: [max |y| bits, scale exponent, pad][nt int64 sums].
   unsigned long long* acc = nullptr;
-  char* scratch = nullptr;
-  TCT_HIP(hipMallocAsync((void**)&scratch, 256 + 8 * (size_t)m->nt, s));
   unsigned* max_bits = (unsigned*)scratch;
   int* scale_exp = (int*)(scratch + 4);
   acc = (unsigned long long*)(scratch + 256);
@@ -1135,9 +1137,66 @@ tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* 
                        (const unsigned long long*)acc, (const int*)scale_exp, xhat, m->nt, accumulate);
     e = hipGetLastError();
   }
-  (void)hipFreeAsync(scratch, s);
   if (e != hipSuccess) return hip_fail(e, "reproducible scatter launch");
   return st;
+}
+
+tct_status backproject_fixed(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
+                             const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s) {
+  if (m->nt <= 0) return TCT_OK;
+  char* scratch = nullptr;
+  TCT_HIP(hipMallocAsync((void**)&scratch, fixed_scratch_bytes(m->nt), s));
+  const tct_status st = backproject_fixed_in(m, g, proj, xhat, accumulate, entry, tile_u, a_begin, a_count, s,
+                                             scratch);
+  (void)hipFreeAsync(scratch, s);
+  return st;
+}
+
+// The allocation-free reproducible scatter keeps its scratch in one static
+// device array per GPU, sized for TCT_NOALLOC_MAX_TETS tetrahedra; it lives
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: kernels get the per-device address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current.  Every call on a GPU reuses the same array; the scatter clears
+// what it needs at the start of each call, and calls that overlap in time on
+// one GPU race on it.
+static __device__ __align__(256) unsigned char scratch[256 + 8 * (size_t)TCT_NOALLOC_MAX_TETS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static tct_status static_scratch(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("allocation-free scatter: device id out of range");
+    return TCT_E_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return TCT_OK;
+}
+
+tct_status backproject_fixed_noalloc(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat,
+                                     int accumulate, const int32_t* entry, int tile_u, hipStream_t s) {
+  if (m->nt <= 0) return TCT_OK;
+  if ((int64_t)m->nt > (int64_t)TCT_NOALLOC_MAX_TETS) {
+    set_error("tct_backproject_fixed_noalloc: the mesh has " + std::to_string(m->nt) +
+              " tetrahedra, more than the static scratch holds (TCT_NOALLOC_MAX_TETS = " +
+              std::to_string((long long)TCT_NOALLOC_MAX_TETS) + ")");
+    return TCT_E_ARG;
+  }
+  char* ptr = nullptr;
+  const tct_status st = static_scratch(m->device, &ptr);
+  if (st != TCT_OK) return st;
+  return backproject_fixed_in(m, g, proj, xhat, accumulate, entry, tile_u, 0, g->na, s, ptr);
 }
 
 tct_status entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry, hipStream_t s) {
