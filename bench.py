@@ -124,14 +124,41 @@ def cpu_baseline(w, budget_s):
     t2 = time.time()
     segs = 2 * int(cnt.sum())
     threads = oracle.oracle.max_threads() if o.nthreads == 0 else o.nthreads
+    # The same on one thread, on a sample sized for about a sixth of the budget.
+    o.nthreads = 1
+    rate_all = segs / (t2 - t0)
+    k1 = max(1, n // max(1, int(budget_s / 6.0 * rate_all / threads / (2 * seg_per_ray))))
+    ids1 = np.arange(0, n, k1, dtype=np.int64)
+    t3 = time.time()
+    b1, cnt1 = o.forward(w.x, ids1, return_counts=True)
+    o.backproject(b1.astype(np.float32), ids1)
+    t4 = time.time()
+    o.nthreads = 0
     return {
-        "value": segs / (t2 - t0),
+        "value": rate_all,
         "unit": "tet-segments/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"every {k}-th ray ({len(ids)} rays, {segs} segments fwd+back) of the same workload; "
                   f"forward {t1 - t0:.1f}s, backprojection {t2 - t1:.1f}s; mesh build {build_s:.1f}s untimed",
+        "single_thread_value": 2 * int(cnt1.sum()) / (t4 - t3),
+        "single_thread_sample": f"every {k1}-th ray ({len(ids1)} rays), forward + backprojection {t4 - t3:.1f}s",
+        "cpu_model": cpu_model(),
     }
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo) and logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs visible, {len(os.sched_getaffinity(0))} usable)"
 
 
 def init_sweep_bench(args):
