@@ -236,11 +236,15 @@ tct_status tct_entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry
 tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
                        tct_stream s);
 
-#define TCT_BP_ATOMIC 0        /* ray-driven float32 scatter (Section II-F); each 16x16-pixel block first sums
-                                  its segments per tetrahedron in on-chip memory (64-bit fixed point scaled to
-                                  the block's largest |y_j| |P_j - S|: every term is kept to 2^-54 of it),
-                                  then adds one float atomic per distinct tetrahedron to xhat */
-#define TCT_BP_GATHER 1        /* deterministic: per-tetrahedron lists of (ray, length), summed in ray order */
+#define TCT_BP_ATOMIC 0        /* ray-driven float32 scatter (Section II-F); each wavefront (an 8x8-pixel tile)
+                                  first sums its segments per tetrahedron in on-chip memory over windows of
+                                  steps (64-bit fixed point scaled to the wavefront's largest |y_j| |P_j - S|:
+                                  every term is kept to 2^-54 of it), then adds one float atomic per distinct
+                                  tetrahedron to xhat */
+#define TCT_BP_GATHER 1        /* deterministic: explicit per-tetrahedron lists of the wavefronts' exact
+                                  fixed-point partial sums (one per wavefront and window of steps that crosses
+                                  the tetrahedron), each list added exactly as 128-bit integers, so the sum does
+                                  not depend on the order of the list */
 #define TCT_BP_ATOMIC_DIRECT 2 /* one float32 atomic add to xhat per segment, as in the paper */
 #define TCT_BP_FIXED 4         /* reproducible ray-driven scatter: the atomic walk with every term rounded to
                                   a multiple of 2^-s, one s per launch (terms stay below 2^(62 - ceil(log2
@@ -418,6 +422,12 @@ tct_status tct_batch_backproject(tct_batch* b, const tct_vecset* proj, const tct
                                  tct_stream s);
 /* Total pixel blocks (queue items) of the batch. */
 int64_t tct_batch_items(const tct_batch* b);
+/* Pixel blocks a workgroup of the persistent batched launch takes from the
+ * work queue per fetch (1..64, default 1; else TCT_E_ARG).  The pixel block
+ * shape follows the paper's thread-block tuning (Section II-F); the queue
+ * granularity is the batched launch's second tuned knob.  Applies to later
+ * tct_batch_forward / tct_batch_backproject calls. */
+tct_status tct_batch_set_queue_chunk(tct_batch* b, int32_t blocks_per_fetch);
 void tct_batch_destroy(tct_batch* b);
 
 /* ---------------------------------------------------------------- misc */

@@ -116,6 +116,7 @@ _SIGS = {
     "tct_batch_forward": (C.c_int, [_P, _P, _P, _P]),
     "tct_batch_backproject": (C.c_int, [_P, _P, _P, C.c_int, _P]),
     "tct_batch_items": (C.c_int64, [_P]),
+    "tct_batch_set_queue_chunk": (C.c_int, [_P, C.c_int32]),
     "tct_batch_destroy": (None, [_P]),
     "tct_last_error": (C.c_char_p, []),
     "tct_version": (C.c_char_p, []),

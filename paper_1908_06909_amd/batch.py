@@ -91,6 +91,12 @@ class BatchProjector:
         self._h = h
         self.items = int(lib().tct_batch_items(h))
         self.tile_u = list(tile_u) if tile_u is not None else [8] * n
+        self.queue_chunk = 1
+
+    def set_queue_chunk(self, blocks_per_fetch: int):
+        """Pixel blocks a workgroup takes from the work queue per fetch (1..64)."""
+        call("tct_batch_set_queue_chunk", self._h, int(blocks_per_fetch))
+        self.queue_chunk = int(blocks_per_fetch)
 
     def forward(self, x: VecSet, proj: VecSet):
         call("tct_batch_forward", self._h, x.handle, proj.handle, _stream(self.device))

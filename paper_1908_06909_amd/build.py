@@ -2,8 +2,8 @@
 
 Every source is compiled by hipcc as HIP (host and device passes) with
 floating-point contraction off (ray endpoints and the certified sign filters
-depend on the exact float32 rounding of each operation) and packed-FP32
-instructions disabled.
+depend on the exact float32 rounding of each operation), packed-FP32
+instructions disabled and the compiler's wave-level atomic combining off.
 """
 
 from __future__ import annotations
@@ -32,6 +32,11 @@ FLAGS = [
     "-fno-fast-math",
     "-fno-gpu-rdc",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Atomics on a wave-uniform address stay per lane: the walk's rare-event
+    # counters sit in branches the common path skips, and the wave-level
+    # combining the compiler would add costs scalar registers in the step
+    # loop.
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -260,8 +260,8 @@ tct_status tct_entry(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_s
     return TCT_E_ARG;
   }
   DeviceGuard dg(m->device);
-  return launch_pixel_walk(kModeEntry, m, g, 0, g->na, nullptr, nullptr, nullptr, entry, nullptr, nullptr, nullptr,
-                           nullptr, default_tile_u(), (hipStream_t)s);
+  return launch_pixel_walk(kModeEntry, m, g, 0, g->na, nullptr, nullptr, nullptr, entry, nullptr, default_tile_u(),
+                           (hipStream_t)s);
 }
 
 tct_status tct_entry_rstar(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s) {
@@ -276,8 +276,8 @@ tct_status tct_entry_rstar(const tct_mesh* m, const tct_geom* g, int32_t* entry,
     return TCT_E_ARG;
   }
   DeviceGuard dg(m->device);
-  return launch_pixel_walk(kModeEntryRstar, m, g, 0, g->na, nullptr, nullptr, nullptr, entry, nullptr, nullptr,
-                           nullptr, nullptr, default_tile_u(), (hipStream_t)s);
+  return launch_pixel_walk(kModeEntryRstar, m, g, 0, g->na, nullptr, nullptr, nullptr, entry, nullptr,
+                           default_tile_u(), (hipStream_t)s);
 }
 
 tct_status tct_entry_raster(const tct_mesh* m, const tct_geom* g, int32_t* entry, tct_stream s) {
@@ -315,8 +315,8 @@ tct_status tct_forward_range(const tct_mesh* m, const tct_geom* g, const float* 
     return TCT_E_ARG;
   }
   DeviceGuard dg(m->device);
-  return launch_pixel_walk(kModeForward, m, g, r->a0, r->na, entry, x, proj, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, r->tile_u, (hipStream_t)s);
+  return launch_pixel_walk(kModeForward, m, g, r->a0, r->na, entry, x, proj, nullptr, nullptr, r->tile_u,
+                           (hipStream_t)s);
 }
 
 tct_status tct_backproject_range(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
@@ -342,8 +342,8 @@ tct_status tct_backproject_range(const tct_mesh* m, const tct_geom* g, const flo
     st = launch_fill(xhat, m->nt, 0.f, (hipStream_t)s);
     if (st != TCT_OK) return st;
   }
-  return launch_pixel_walk(kModeBackAtomic, m, g, r->a0, r->na, entry, proj, xhat, nullptr, nullptr, nullptr,
-                           nullptr, nullptr, r->tile_u, (hipStream_t)s, mode == TCT_BP_ATOMIC);
+  return launch_pixel_walk(kModeBackAtomic, m, g, r->a0, r->na, entry, proj, xhat, nullptr, nullptr, r->tile_u,
+                           (hipStream_t)s, mode == TCT_BP_ATOMIC);
 }
 
 tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, float* proj, const int32_t* entry,
@@ -355,8 +355,8 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
     return TCT_E_ARG;
   }
   DeviceGuard dg(m->device);
-  return launch_pixel_walk(kModeForward, m, g, 0, g->na, entry, x, proj, nullptr, nullptr, nullptr, nullptr, nullptr,
-                           default_tile_u(), (hipStream_t)s);
+  return launch_pixel_walk(kModeForward, m, g, 0, g->na, entry, x, proj, nullptr, nullptr, default_tile_u(),
+                           (hipStream_t)s);
 }
 
 tct_status tct_backproject(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int mode,
@@ -691,6 +691,15 @@ tct_status tct_batch_backproject(tct_batch* b, const tct_vecset* proj, const tct
     if (st != TCT_OK) return st;
   }
   return batch_walk(b, kModeBackAtomic, proj, xhat, (hipStream_t)s);
+}
+
+tct_status tct_batch_set_queue_chunk(tct_batch* b, int32_t blocks_per_fetch) {
+  if (!b || blocks_per_fetch < 1 || blocks_per_fetch > 64) {
+    set_error("tct_batch_set_queue_chunk: blocks per fetch must be 1..64");
+    return TCT_E_ARG;
+  }
+  b->queue_chunk = blocks_per_fetch;
+  return TCT_OK;
 }
 
 int64_t tct_batch_items(const tct_batch* b) { return b ? b->total_items : 0; }

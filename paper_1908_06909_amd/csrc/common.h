@@ -160,6 +160,7 @@ struct tct_batch {
   int64_t total_items = 0;
   unsigned long long* d_counter = nullptr;
   int grid_fwd = 0, grid_bwd = 0;  // persistent grid sizes
+  int queue_chunk = 1;             // pixel blocks handed out per queue fetch
 };
 
 struct tct_geom {

@@ -1,24 +1,27 @@
-// Deterministic backprojection: xhat_i = sum_j a_ij y_j (Eq. 3) summed per
-// tetrahedron in a fixed order, so the result is bitwise reproducible.
+// Deterministic backprojection: xhat_i = sum_j a_ij y_j (Eq. 3) over explicit
+// per-tetrahedron lists, summed exactly, so the result is bitwise
+// reproducible.
 //
 // The paper scatters with atomics (Section II-F), having found a variant
 // that kept the rays' contributions apart slower on its GPU; the atomic path
-// (walk.hip) is the fast one here too.  This path trades speed for
+// (walk.hip) is the fast one here too.  This path trades some speed for
 // reproducibility.  Per chunk of angles:
-//   1. count walk: positive-length visits per ray, reduced to the longest
-//      list of each wavefront;
-//   2. exclusive scan -> each wavefront's slot range (64 x its longest list);
-//   3. fill walk: (tetrahedron, a_ij y_j) pairs, segment k of lane l at
-//      base + 64 k + l, so each step stores 64 consecutive words; shorter
-//      lists padded with key nt;
-//   4. stable LSD radix sort by tetrahedron (slot order kept within a key);
-//   5. run boundaries from the sorted keys; one wavefront per tetrahedron
-//      sums its run in float64 (lane l takes elements l, l+64, ... in order,
-//      then a fixed butterfly), added to a float64 accumulator; chunks are
-//      added in angle order.
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
-
+//   1. fill walk: every wavefront sums its segments per tetrahedron over a
+//      window of steps in its LDS table, exactly, in 64-bit fixed point with
+//      the wavefront's own power-of-two scale, and at the end of each window
+//      writes one record (tetrahedron, scale, integer sum) per tetrahedron
+//      it met, counting the records of each tetrahedron;
+//   2. exclusive scan of the counts -> each tetrahedron's list;
+//   3. scatter of the records into their tetrahedron's list (the order
+//      inside a list depends on timing);
+//   4. one wavefront per tetrahedron adds its list exactly: every record is
+//      brought to the list's finest scale (or, when the list's scales are
+//      more than 36 powers of two apart, to 36 above its coarsest, the finer
+//      records truncated there), summed as 128-bit integers, and the sum is
+//      converted to float64 once, so the result does not depend on the
+//      order; chunks are added in angle order.
+// The records are some fourteen times fewer than the segments (the
+// wavefront's 64 rays cross each tetrahedron together).
 #include "common.h"
 #include "kernels.h"
 
@@ -31,48 +34,88 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
-__global__ void zero_i64_kernel(int64_t* p, int64_t n) {
+__global__ void zero_i32_kernel(int32_t* p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
 
-// Run boundaries of the sorted keys: [run[2 t], run[2 t + 1]) holds
-// tetrahedron t (both zero when it has no segment); padding keys (>= nt)
-// are skipped.
-// Each thread takes kRunItems consecutive keys.
-constexpr int kRunItems = 8;
+__global__ void zero_u64_one_kernel(unsigned long long* p) { *p = 0ull; }
 
-__global__ void run_bounds_kernel(const int32_t* keys, int64_t n, int nt, int64_t* run) {
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRunItems;
-  if (i0 >= n) return;
-  int prev = i0 > 0 ? keys[i0 - 1] : -1;
-#pragma unroll
-  for (int u = 0; u < kRunItems; ++u) {
-    const int64_t i = i0 + u;
-    if (i >= n) break;
-    const int k = keys[i];
-    const int next = i + 1 < n ? keys[i + 1] : -1;
-    if (k < nt) {
-      if (prev != k) run[2 * (int64_t)k] = i;
-      if (next != k) run[2 * (int64_t)k + 1] = i + 1;
-    }
-    prev = k;
-  }
+// Records into their tetrahedron's list: list t is [off[t], off[t] + counts
+// of t); cur[t] (zeroed) hands out its positions.
+__global__ void scatter_records_kernel(const int32_t* tet, const int32_t* scale, const int64_t* m, int64_t n,
+                                       const int64_t* off, int32_t* cur, int32_t* sscale, int64_t* sm) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int t = tet[r];
+  const int64_t p = off[t] + atomicAdd(cur + t, 1);
+  sscale[p] = scale[r];
+  sm[p] = m[r];
 }
 
-// One wavefront per tetrahedron.
-__global__ __launch_bounds__(256) void segment_sum_kernel(const int64_t* run, const float* vals, double* acc,
-                                                          int nt) {
-  int t = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  int lane = threadIdx.x & 63;
+// 128-bit two's complement integers for exact sums.
+struct I128 {
+  unsigned long long lo;
+  long long hi;
+};
+
+__device__ __forceinline__ I128 i128_add(I128 a, I128 b) {
+  I128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1 : 0);
+  return r;
+}
+
+// m 2^k exactly for 0 <= k <= 36 (|m| < 2^60, so |m 2^k| < 2^96 and up to 2^30
+// of them add up below 2^127), floor(m 2^k) for k < 0.
+__device__ __forceinline__ I128 i128_scaled(long long m, int k) {
+  I128 r;
+  if (k > 0) {
+    r.lo = (unsigned long long)m << k;
+    r.hi = m >> (64 - k);
+  } else {
+    const long long v = k < 0 ? (k > -64 ? m >> -k : (m < 0 ? -1 : 0)) : m;
+    r.lo = (unsigned long long)v;
+    r.hi = v >> 63;
+  }
+  return r;
+}
+
+// One wavefront per tetrahedron: its list summed exactly (see step 4).
+constexpr int kSumWaves = 4;
+constexpr int kMaxScaleSpread = 36;
+
+__global__ __launch_bounds__(64 * kSumWaves) void exact_sum_kernel(const int64_t* off, const int32_t* sscale,
+                                                                   const int64_t* sm, double* acc, int nt) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * kSumWaves + (threadIdx.x >> 6);
   if (t >= nt) return;
-  const int64_t b = run[2 * (int64_t)t], e = run[2 * (int64_t)t + 1];
+  const int64_t b = off[t], e = off[t + 1];
   if (b == e) return;
-  double s = 0.0;
-  for (int64_t i = b + lane; i < e; i += 64) s += (double)vals[i];
+  int smin = 1 << 30, smax = -(1 << 30);
+  for (int64_t i = b + lane; i < e; i += 64) {
+    const int sc = sscale[i];
+    smin = min(smin, sc);
+    smax = max(smax, sc);
+  }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-  if (lane == 0) acc[t] += s;
+  for (int o = 1; o < 64; o <<= 1) {
+    smin = min(smin, __shfl_xor(smin, o, 64));
+    smax = max(smax, __shfl_xor(smax, o, 64));
+  }
+  const int sref = min(smax, smin + kMaxScaleSpread);
+  I128 s{0ull, 0ll};
+  for (int64_t i = b + lane; i < e; i += 64) s = i128_add(s, i128_scaled(sm[i], sref - sscale[i]));
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    I128 x;
+    x.lo = ((unsigned long long)(unsigned)__shfl_xor((int)(s.lo >> 32), o, 64) << 32) |
+           (unsigned)__shfl_xor((int)s.lo, o, 64);
+    x.hi = (long long)(((unsigned long long)(unsigned)__shfl_xor((int)(s.hi >> 32), o, 64) << 32) |
+                       (unsigned)__shfl_xor((int)s.hi, o, 64));
+    s = i128_add(s, x);
+  }
+  if (lane == 0) acc[t] += ldexp((double)s.hi, 64 - sref) + ldexp((double)s.lo, -sref);
 }
 
 __global__ void finish_kernel(const double* acc, float* xhat, int nt, int accumulate) {
@@ -101,83 +144,144 @@ struct AsyncBuf {
   }
 };
 
-int key_bits(int nt) {
-  int b = 1;
-  while ((1ll << b) < (long long)nt) ++b;
-  return b;
-}
+unsigned grid_of(int64_t n, int per_block) { return (unsigned)std::max<int64_t>(1, (n + per_block - 1) / per_block); }
 
 }  // namespace
 
-tct_status exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_host, hipStream_t s) {
-  // out has n + 1 entries; out[n] is the total.
-  size_t tmp_bytes = 0;
-  TCT_HIP(rocprim::inclusive_scan(nullptr, tmp_bytes, in, out + 1, (size_t)n, rocprim::plus<int64_t>(), s));
-  AsyncBuf<char> tmp(s);
-  TCT_HIP(tmp.ensure(tmp_bytes));
-  int64_t zero = 0;
-  TCT_HIP(hipMemcpyAsync(out, &zero, sizeof(int64_t), hipMemcpyHostToDevice, s));
-  TCT_HIP(rocprim::inclusive_scan(tmp.p, tmp_bytes, in, out + 1, (size_t)n, rocprim::plus<int64_t>(), s));
-  if (total_host) {
-    TCT_HIP(hipMemcpyAsync(total_host, out + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    TCT_HIP(hipStreamSynchronize(s));
+// Exclusive scan of n int32 counts into n + 1 int64 offsets (out[n] = the
+// total), in three launches: per-block sums of kScanItems counts, a scan of
+// those sums by one block, then each block's own scan from its offset.
+namespace {
+constexpr int kScanItems = 2048;  // counts per block (256 threads x 8)
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t s_w[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
+  if (lane == 63) s_w[w] = x;
+  __syncthreads();
+  int64_t before = 0;
+  for (int k = 0; k < w; ++k) before += s_w[k];
+  *total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+  __syncthreads();
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(256) void scan_sums_kernel(const int32_t* in, int64_t n, int64_t* sums) {
+  const int64_t i0 = (int64_t)blockIdx.x * kScanItems + threadIdx.x * 8;
+  int64_t v = 0;
+  for (int u = 0; u < 8; ++u)
+    if (i0 + u < n) v += in[i0 + u];
+  int64_t total;
+  (void)block_exclusive_scan(v, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block scans the block sums in place (exclusive) and writes the total.
+__global__ __launch_bounds__(256) void scan_top_kernel(int64_t* sums, int64_t nb, int64_t* total_out) {
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = i < nb ? sums[i] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(v, &total);
+    if (i < nb) sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(256) void scan_out_kernel(const int32_t* in, int64_t n, const int64_t* sums,
+                                                       int64_t* out) {
+  const int64_t i0 = (int64_t)blockIdx.x * kScanItems + threadIdx.x * 8;
+  int64_t c[8], v = 0;
+  for (int u = 0; u < 8; ++u) {
+    c[u] = i0 + u < n ? in[i0 + u] : 0;
+    v += c[u];
+  }
+  int64_t total;
+  int64_t x = sums[blockIdx.x] + block_exclusive_scan(v, &total);
+  for (int u = 0; u < 8; ++u) {
+    if (i0 + u < n) out[i0 + u] = x;
+    x += c[u];
+  }
+}
+}  // namespace
+
+tct_status exclusive_scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t* sums, hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanItems - 1) / kScanItems);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3((unsigned)nb), dim3(256), 0, s, in, n, sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(256), 0, s, sums, nb, out + n);
+  hipLaunchKernelGGL(scan_out_kernel, dim3((unsigned)nb), dim3(256), 0, s, in, n, (const int64_t*)sums, out);
+  TCT_HIP(hipGetLastError());
   return TCT_OK;
 }
 
 tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
                               const int32_t* entry, int tile_u, int a_begin, int a_count, hipStream_t s) {
+  const int nt = m->nt;
   const int64_t rays_per_angle = (int64_t)g->cone.nu * g->cone.nv;
-  // Chunk of angles: about 4M rays, at least one angle.
-  int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(a_count, ((int64_t)1 << 22) / rays_per_angle));
+  // Records per chunk: a budget of 2^28 (8 GB of records and lists); the
+  // first chunk is sized from a guess of 16 records per ray and later ones
+  // from the records per angle seen so far.
+  const int64_t kBudget = (int64_t)1 << 28;
   AsyncBuf<double> acc(s);
-  AsyncBuf<int64_t> counts(s), offsets(s);
-  AsyncBuf<int32_t> keys(s), keys_sorted(s);
-  AsyncBuf<float> vals(s), vals_sorted(s);
-  AsyncBuf<char> sort_tmp(s);
-  AsyncBuf<int64_t> run(s);
-  TCT_HIP(acc.ensure(m->nt));
-  TCT_HIP(run.ensure(2 * (size_t)m->nt));
-  hipLaunchKernelGGL(zero_f64_kernel, dim3((m->nt + 255) / 256), dim3(256), 0, s, acc.p, (int64_t)m->nt);
+  AsyncBuf<int32_t> counts(s), rtet(s), rscale(s), sscale(s);
+  AsyncBuf<int64_t> scan_sums(s), offsets(s), rm(s), sm(s);
+  AsyncBuf<unsigned long long> cursor(s);
+  TCT_HIP(acc.ensure(nt));
+  TCT_HIP(counts.ensure(nt));
+  TCT_HIP(scan_sums.ensure((size_t)nt / kScanItems + 1));
+  TCT_HIP(offsets.ensure((size_t)nt + 1));
+  TCT_HIP(cursor.ensure(1));
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, acc.p, (int64_t)nt);
   TCT_HIP(hipGetLastError());
-  const int bits = key_bits(m->nt + 1);  // padding key nt included
+  double rec_per_angle = 16.0 * (double)rays_per_angle;
   const int a_end = a_begin + a_count;
-  for (int a0 = a_begin; a0 < a_end; a0 += chunk) {
-    int na_c = std::min(chunk, a_end - a0);
-    const int64_t nw = pixel_walk_waves(g, na_c, tile_u);
-    TCT_HIP(counts.ensure(nw));
-    TCT_HIP(offsets.ensure(nw + 1));
-    tct_status st = launch_pixel_walk(kModeCountPos, m, g, a0, na_c, entry, proj, nullptr, nullptr, counts.p,
-                                      nullptr, nullptr, nullptr, tile_u, s);
-    if (st != TCT_OK) return st;
+  int a0 = a_begin;
+  while (a0 < a_end) {
+    int na_c = (int)std::max<double>(1.0, std::min<double>(a_end - a0, std::floor(kBudget / rec_per_angle)));
+    int64_t cap = std::max<int64_t>(1024, (int64_t)(rec_per_angle * na_c * 1.25));
     int64_t total = 0;
-    st = exclusive_scan_i64(counts.p, offsets.p, nw, &total, s);
-    if (st != TCT_OK) return st;
-    if (total == 0) continue;
-    TCT_HIP(keys.ensure(total));
-    TCT_HIP(vals.ensure(total));
-    TCT_HIP(keys_sorted.ensure(total));
-    TCT_HIP(vals_sorted.ensure(total));
-    st = launch_pixel_walk(kModeGatherFill, m, g, a0, na_c, entry, proj, nullptr, nullptr, nullptr, offsets.p, keys.p,
-                           vals.p, tile_u, s);
-    if (st != TCT_OK) return st;
-    size_t tmp_bytes = 0;
-    TCT_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys.p, keys_sorted.p, vals.p, vals_sorted.p,
-                                      (size_t)total, 0, bits, s));
-    TCT_HIP(sort_tmp.ensure(tmp_bytes));
-    TCT_HIP(rocprim::radix_sort_pairs(sort_tmp.p, tmp_bytes, keys.p, keys_sorted.p, vals.p, vals_sorted.p,
-                                      (size_t)total, 0, bits, s));
-    const int64_t nrun = 2 * (int64_t)m->nt;
-    hipLaunchKernelGGL(zero_i64_kernel, dim3((unsigned)((nrun + 255) / 256)), dim3(256), 0, s, run.p, nrun);
-    const int64_t run_threads = (total + kRunItems - 1) / kRunItems;
-    hipLaunchKernelGGL(run_bounds_kernel, dim3((unsigned)((run_threads + 255) / 256)), dim3(256), 0, s,
-                       keys_sorted.p, total, m->nt, run.p);
-    int64_t threads = (int64_t)m->nt * 64;
-    hipLaunchKernelGGL(segment_sum_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, run.p,
-                       vals_sorted.p, acc.p, m->nt);
-    TCT_HIP(hipGetLastError());
+    for (;;) {
+      TCT_HIP(rtet.ensure(cap));
+      TCT_HIP(rscale.ensure(cap));
+      TCT_HIP(rm.ensure(cap));
+      hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, counts.p, (int64_t)nt);
+      hipLaunchKernelGGL(zero_u64_one_kernel, dim3(1), dim3(1), 0, s, cursor.p);
+      TCT_HIP(hipGetLastError());
+      const GatherOut go{rtet.p, rscale.p, rm.p, counts.p, cursor.p, cap};
+      tct_status st = launch_pixel_walk(kModeGatherFill, m, g, a0, na_c, entry, proj, nullptr, nullptr, &go, tile_u,
+                                        s);
+      if (st != TCT_OK) return st;
+      unsigned long long need = 0;
+      TCT_HIP(hipMemcpyAsync(&need, cursor.p, sizeof(need), hipMemcpyDeviceToHost, s));
+      TCT_HIP(hipStreamSynchronize(s));
+      total = (int64_t)need;
+      if (total <= cap) break;
+      cap = total + total / 8;  // every record fits on the second pass
+    }
+    rec_per_angle = std::max(1.0, (double)total / na_c);
+    if (total > 0) {
+      TCT_HIP(sscale.ensure(total));
+      TCT_HIP(sm.ensure(total));
+      tct_status st = exclusive_scan_counts(counts.p, offsets.p, nt, scan_sums.p, s);
+      if (st != TCT_OK) return st;
+      hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, counts.p, (int64_t)nt);
+      hipLaunchKernelGGL(scatter_records_kernel, dim3(grid_of(total, 256)), dim3(256), 0, s, rtet.p, rscale.p, rm.p,
+                         total, offsets.p, counts.p, sscale.p, sm.p);
+      hipLaunchKernelGGL(exact_sum_kernel, dim3(grid_of(nt, kSumWaves)), dim3(64 * kSumWaves), 0, s, offsets.p,
+                         sscale.p, sm.p, acc.p, nt);
+      TCT_HIP(hipGetLastError());
+    }
+    a0 += na_c;
   }
-  hipLaunchKernelGGL(finish_kernel, dim3((m->nt + 255) / 256), dim3(256), 0, s, acc.p, xhat, m->nt, accumulate);
+  hipLaunchKernelGGL(finish_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, acc.p, xhat, nt, accumulate);
   TCT_HIP(hipGetLastError());
   return TCT_OK;
 }

@@ -10,7 +10,6 @@ enum WalkMode {
   kModeForward = 1,
   kModeBackAtomic = 2,
   kModeCountAll = 3,
-  kModeCountPos = 4,
   kModeTrace = 5,
   kModeGatherFill = 6,
   kModeBackDirect = 7,  // backprojection with one global atomic per segment
@@ -18,11 +17,25 @@ enum WalkMode {
   kModeBackFixed = 9,   // backprojection through the block table into 64-bit fixed-point sums (reproducible)
 };
 
+// Explicit per-tetrahedron lists (TCT_BP_GATHER): records of one chunk of
+// angles, each the exact fixed-point sum m 2^-scale over the rays of one
+// wavefront and one window of steps that cross tetrahedron `tet` with
+// positive length (scale: the wavefront's, a power of two).  counts[tet]
+// counts the tetrahedron's records; cursor counts all records, also those
+// beyond cap, which are not written.
+struct GatherOut {
+  int32_t* tet;
+  int32_t* scale;
+  int64_t* m;
+  int32_t* counts;
+  unsigned long long* cursor;
+  int64_t cap;
+};
+
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
                              const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
-                             int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
-                             hipStream_t s, int lds_table = 0, unsigned long long* acc64 = nullptr,
-                             const int* scale_exp = nullptr);
+                             const GatherOut* gather, int tile_u, hipStream_t s, int lds_table = 0,
+                             unsigned long long* acc64 = nullptr, const int* scale_exp = nullptr);
 
 tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float* proj, float* xhat, int accumulate,
                               const int32_t* entry, int tile_u, int lds_table, hipStream_t s);
@@ -63,7 +76,7 @@ tct_status vecset_xpay_ratio(const tct_vecset* p, const tct_vecset* x, const dou
                              hipStream_t s);
 tct_status vecset_fill(const tct_vecset* y, float v, hipStream_t s);
 
-tct_status exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* total_host, hipStream_t s);
+tct_status exclusive_scan_counts(const int32_t* in, int64_t* out, int64_t n, int64_t* sums, hipStream_t s);
 
 // Host-side builders (mesh.cpp).
 tct_status mesh_build(const float* verts, int32_t nv, const int32_t* tets, int32_t nt, const int32_t* nbrs,

@@ -40,9 +40,32 @@ namespace tct {
 
 namespace {
 
-// Per-lane walk statistics (events of one ray; reduced per wave at the end).
-struct LaneStats {
+// Pointers into LDS (32-bit addresses; atomics through them are native LDS
+// atomics, not flat ones).
+typedef __attribute__((address_space(3))) unsigned lds_u32;
+typedef __attribute__((address_space(3))) int lds_i32;
+typedef __attribute__((address_space(3))) long long lds_i64;
+
+// The wavefront index within the block, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Walk statistics, in two forms with the same interface.  RegStats keeps
+// every count in a lane register (the forward, trace and entry walks, where
+// a register costs nothing and a branch per step would).  LdsStats keeps
+// only the step count per lane and adds the rare events (zero-length
+// passages, float64 and exact sign evaluations, perturbed ties, failures,
+// float64 crossings) straight to the wavefront's own counters in LDS, which
+// frees the registers the scatter walks need for their table.  flush_stats
+// adds either to the mesh's counters once per wavefront.
+enum Event { kEvZero = 0, kEvFp64, kEvExact, kEvPert, kEvFailed, kEvGrazing, kEvRays, kEvSteps, kEvents };
+
+__device__ __forceinline__ void lds_add_u32(lds_u32* p, unsigned v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+struct RegStats {
   int steps = 0, zero = 0, fp64 = 0, exact = 0, pert = 0, failed = 0, grazing = 0;
+  __device__ __forceinline__ explicit RegStats(lds_u32*) {}
   __device__ __forceinline__ void add_zero() { zero++; }
   __device__ __forceinline__ void add_grazing() { grazing++; }
   __device__ __forceinline__ void add_fp64() { fp64++; }
@@ -50,6 +73,28 @@ struct LaneStats {
   __device__ __forceinline__ void add_pert() { pert++; }
   __device__ __forceinline__ void add_failed() { failed++; }
 };
+
+struct LdsStats {
+  int steps = 0;
+  lds_u32* ev;  // this wavefront's kEvents counters in LDS
+  __device__ __forceinline__ explicit LdsStats(lds_u32* wave_counters) : ev(wave_counters) {}
+  __device__ __forceinline__ void add_zero() { lds_add_u32(ev + kEvZero, 1u); }
+  __device__ __forceinline__ void add_grazing() { lds_add_u32(ev + kEvGrazing, 1u); }
+  __device__ __forceinline__ void add_fp64() { lds_add_u32(ev + kEvFp64, 1u); }
+  __device__ __forceinline__ void add_exact() { lds_add_u32(ev + kEvExact, 1u); }
+  __device__ __forceinline__ void add_pert() { lds_add_u32(ev + kEvPert, 1u); }
+  __device__ __forceinline__ void add_failed() { lds_add_u32(ev + kEvFailed, 1u); }
+};
+
+// The calling wavefront's event counters in the block's table `all`
+// (kEvents per wavefront), cleared.
+__device__ __forceinline__ lds_u32* wave_counters(unsigned* all) {
+  lds_u32* ev = (lds_u32*)all + kEvents * wave_in_block();
+  if ((threadIdx.x & 63) < kEvents) ev[threadIdx.x & 63] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  return ev;
+}
 
 // Pixel ray S -> P(u, v) of one angle's frame.
 __device__ __forceinline__ Ray cone_ray(const GeomView& g, float mesh_extent, int a, int i, int j) {
@@ -103,7 +148,8 @@ __device__ __noinline__ double crossing_s_fp64(float3 S, float3 P, float3 on, fl
 }
 
 
-__device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, LaneStats& st) {
+template <class St>
+__device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 q, St& st) {
   if (fast != 2) return fast;
   int res = slow_edge_sign(r.S, r.P, r.U, r.V, p, q);
   st.add_fp64();
@@ -112,8 +158,8 @@ __device__ __forceinline__ int resolve(int fast, const Ray& r, float3 p, float3 
   return (res & 3) - 1;
 }
 
-template <class Src>
-__device__ __forceinline__ int resolve_src(const Src& q, float3 a, float3 b, LaneStats& st) {
+template <class Src, class St>
+__device__ __forceinline__ int resolve_src(const Src& q, float3 a, float3 b, St& st) {
   int res = slow_edge_sign(q.S(), q.P(), q.U(), q.V(), a, b);
   st.add_fp64();
   if (res & (kFlagExact << 2)) st.add_exact();
@@ -122,7 +168,8 @@ __device__ __forceinline__ int resolve_src(const Src& q, float3 a, float3 b, Lan
 }
 
 // Exact entry test for boundary face b (slots in outward order).
-__device__ bool enters_face(const MeshView& M, const Ray& r, int b, LaneStats& st) {
+template <class St>
+__device__ bool enters_face(const MeshView& M, const Ray& r, int b, St& st) {
   const float4* q = M.bfaces + 4 * (size_t)b;
   float4 q0 = q[0], q1 = q[1], q2 = q[2];
   float3 a0 = make_float3(q0.x, q0.y, q0.z), a1 = make_float3(q1.x, q1.y, q1.z), a2 = make_float3(q2.x, q2.y, q2.z);
@@ -166,9 +213,9 @@ __device__ __forceinline__ bool line_hits_box(const Ray& r, float3 inv, const Bv
 // through exactly one face, so the first face passing the exact entry test
 // is the answer.  BVH leaves hold a contiguous range of faces
 // (first * 8 + count); R*-tree leaves index a face list (first * 16 + count).
-template <bool kRstar>
+template <bool kRstar, class St>
 __device__ int scan_tree(const MeshView& M, const BvhNode* tree, const Ray& r, float3 inv, int node, int end,
-                         LaneStats& st) {
+                         St& st) {
   while (node >= 0 && node != end) {
     const float4* np = reinterpret_cast<const float4*>(tree + node);
     float4 n0 = np[0], n1 = np[1];
@@ -211,8 +258,8 @@ __device__ int scan_tree(const MeshView& M, const BvhNode* tree, const Ray& r, f
 // group is skipped when the smallest d . n over its normals' bounding box is
 // positive (beyond the rounding of that bound: products of |n| <= 1 with d,
 // three of them summed, err below 3u |d|_1; the margin is 1e-6 |d|_1).
-template <bool kRstar = false>
-__device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
+template <bool kRstar = false, class St>
+__device__ int find_entry(const MeshView& M, const Ray& r, St& st) {
   float3 inv = make_float3(1.0f / r.d.x, 1.0f / r.d.y, 1.0f / r.d.z);
   if constexpr (kRstar) {
     return scan_tree<true>(M, M.rstar, r, inv, 0, -1, st);
@@ -232,60 +279,89 @@ __device__ int find_entry(const MeshView& M, const Ray& r, LaneStats& st) {
   }
 }
 
-// Per-block accumulation table for the backprojection.  Neighbouring rays
-// of a pixel block cross mostly the same tetrahedra (at the benchmark pitch a
-// 16 x 16 block spans about two elements), so scattering every segment with a
-// global atomic makes dozens of lanes update one address at once.  Instead
-// each block sums its segments per tetrahedron in an LDS open-addressing
-// table (key = tetrahedron, linear probing) and adds one global atomic per
-// distinct tetrahedron when it flushes the table.  A 16 x 16 bundle crosses
-// some 4000 tetrahedra on its way through the benchmark mesh, more than the
-// table holds, so the rays advance in windows of kLdsWindow steps and the
-// table is flushed after each window: it only holds the tetrahedra one
-// window of the bundle touches.  A segment that finds no slot within
-// kLdsProbes probes goes straight to global memory.
+// Per-wavefront accumulation tables for the backprojections.  Neighbouring
+// rays of a pixel tile cross mostly the same tetrahedra (at the benchmark
+// pitch an 8 x 8 tile spans about one element), so scattering every segment
+// with a global atomic makes dozens of lanes update one address at once.
+// Instead each wavefront sums its segments per tetrahedron in its own LDS
+// open-addressing table (key = tetrahedron, linear probing) and adds one
+// global atomic (or, for the explicit lists, writes one record) per distinct
+// tetrahedron when it flushes the table.  The rays advance in windows of a
+// fixed number of steps and the wavefront flushes its table after each
+// window, so the table only holds the tetrahedra of one window of its ray
+// bundle (an 8 x 8 bundle meets about 170 tetrahedra per 32 steps, 300 per
+// 64 steps on the benchmark mesh); a segment that finds no slot within
+// kLdsProbes probes goes straight to global memory.  Tables are private to a
+// wavefront, so a window ends without any block-wide barrier and each
+// wavefront runs at its own pace.  The scatters use small tables and short
+// windows (kScatterSlots, kScatterWindow: fewer registers and less LDS, four
+// wavefronts per SIMD); the explicit lists use longer windows, which make
+// fewer records per segment.
 //
-// The table sums in 64-bit fixed point: LDS integer atomics run several
+// The tables sum in 64-bit fixed point: LDS integer atomics run several
 // times faster than float ones on this chip.  Each term t = L y_j |d| is
-// rounded to a multiple of 2^-54 M, M >= 2^(e-1) the block's largest |y_j| |d|
-// (2^e the next power of two), and at most 256 terms (one per ray of the
-// block) meet in a slot per window, so the integer sum cannot overflow and
-// is exact; the flush converts it back to float.  Every term keeps an
-// absolute error below 2^-54 2^e, far below a float32 rounding of the
-// terms that matter.
-constexpr int kLdsSlots = 4096;
-constexpr int kLdsHashShift = 20;  // multiplicative hash keeps the top 12 bits
-static_assert(kLdsSlots == (1 << (32 - kLdsHashShift)), "hash width must match the table size");
+// rounded to a multiple of 2^-54 M, M >= 2^(e-1) the wavefront's largest
+// |y_j| |d| (2^e the next power of two), and at most 64 terms (one per ray of
+// the wavefront) meet in a slot per window, so the integer sum stays below
+// 2^60 and is exact; the flush converts it back (or records it as it is).
+// Every term keeps an absolute error below 2^-54 2^e, far below a float32
+// rounding of the terms that matter.
+constexpr int kScatterSlots = 384;
+constexpr int kScatterWindow = 24;
+constexpr int kListSlots = 768;
+constexpr int kListWindow = 64;
 constexpr int kLdsProbes = 8;
-constexpr int kLdsWindow = 64;
+constexpr int kBlockWaves = 4;
 
-__device__ __forceinline__ void lds_accumulate(int* keys, long long* vals, int tet, float v, float scale,
-                                               float* xhat, unsigned long long* acc64) {
-  unsigned slot = ((unsigned)tet * 2654435761u) >> kLdsHashShift;
+template <int MODE>
+struct TableShape {
+  static constexpr int slots = MODE == kModeGatherFill ? kListSlots : kScatterSlots;
+  static constexpr int window = MODE == kModeGatherFill ? kListWindow : kScatterWindow;
+};
+
+// Claims an empty slot (-1) for key `tet`; returns the key found there before.
+__device__ __forceinline__ int lds_cas(lds_i32* p, int tet) {
+  int expected = -1;
+  __hip_atomic_compare_exchange_strong(p, &expected, tet, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+  return expected;
+}
+
+template <int kSlots>
+__device__ __forceinline__ unsigned table_home(int tet) {
+  return __umulhi((unsigned)tet * 2654435761u, (unsigned)kSlots);
+}
+
+// Adds v (scaled to fixed point) to the slot of `tet`; false when the
+// tetrahedron finds no slot within kLdsProbes probes (the caller then adds
+// the term elsewhere).
+template <int kSlots>
+__device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int tet, float v, float scale) {
+  unsigned slot = table_home<kSlots>(tet);
   // Most segments find their tetrahedron already placed by a neighbouring
   // ray of the bundle: a plain read settles those without an atomic.
   int k = keys[slot];
-  if (k != tet) k = atomicCAS(keys + slot, -1, tet);
+  if (k != tet) k = lds_cas(keys + slot, tet);
   if (k != -1 && k != tet) {
 #pragma unroll 1
     for (int p = 1; p < kLdsProbes; ++p) {
-      slot = (slot + 1) & (kLdsSlots - 1);
-      k = atomicCAS(keys + slot, -1, tet);
+      slot = slot + 1 == (unsigned)kSlots ? 0u : slot + 1;
+      k = lds_cas(keys + slot, tet);
       if (k == -1 || k == tet) break;
     }
-    if (k != -1 && k != tet) {
-      if (acc64)
-        atomicAdd(acc64 + tet, (unsigned long long)__float2ll_rn(v * scale));
-      else
-        unsafeAtomicAdd(xhat + tet, v);
-      return;
-    }
+    if (k != -1 && k != tet) return false;
   }
-  // The table pointer arrives as a generic pointer; cast it back to the
-  // LDS address space so the add is a native ds_add_u64 (through a generic
-  // pointer it becomes a flat atomic).
-  __hip_atomic_fetch_add((__attribute__((address_space(3))) long long*)(vals + slot), __float2ll_rn(v * scale),
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_add(vals + slot, __float2ll_rn(v * scale), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  return true;
+}
+
+__device__ __forceinline__ void gather_record(const GatherOut& g, int64_t p, int tet, int scale, long long m) {
+  if (p < g.cap) {
+    g.tet[p] = tet;
+    g.scale[p] = scale;
+    g.m[p] = m;
+  }
+  atomicAdd(g.counts + tet, 1);
 }
 
 template <int MODE>
@@ -296,11 +372,14 @@ struct WalkOut {
   // BWD / GATHER_FILL: weight = y_j * |d|
   float weight = 0.f;
   float* xhat = nullptr;
-  int* lds_keys = nullptr;  // per-block accumulation table (BWD), null = direct atomics
-  long long* lds_vals = nullptr;
+  lds_i32* lds_keys = nullptr;  // the wavefront's accumulation table (BWD)
+  lds_i64* lds_vals = nullptr;
   float lds_scale = 1.f;  // fixed-point scale of the table (a power of two)
   unsigned long long* acc64 = nullptr;  // fixed-point result (reproducible mode), else null
-  // TRACE / GATHER_FILL output cursor
+  // GATHER_FILL: records of the explicit lists; key of the current window
+  GatherOut gather{};
+  int scale_exp = 0;  // log2 of lds_scale
+  // TRACE output cursor
   int32_t* out_tet = nullptr;
   float* out_len = nullptr;
   int64_t cursor = 0;
@@ -359,9 +438,9 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, cons
 // One step: leave the current tetrahedron, apply the mode's action for its
 // segment, move to the neighbour.  Returns false once the ray has left the
 // mesh (or the walk failed).
-template <int MODE, class Src>
+template <int MODE, class Src, class St>
 __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const Src& q, WalkState& w,
-                                          WalkOut<MODE>& o, LaneStats& st) {
+                                          WalkOut<MODE>& o, St& st) {
   if (w.steps > M.nt) {
     st.add_failed();
     st.steps += w.steps;
@@ -416,24 +495,28 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   float4 rec = M.faces[(size_t)(((unsigned)tet << 2) | f)];
   if constexpr (MODE == kModeForward) {
     o.acc = fma((double)dt, (double)w.xcur, o.acc);  // the product is exact
-  } else if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed) {
-    if (dt > 0.f) lds_accumulate(o.lds_keys, o.lds_vals, tet, dt * o.weight, o.lds_scale, o.xhat, o.acc64);
+  } else if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
+    if (dt > 0.f) {
+      const float v = dt * o.weight;
+      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, v, o.lds_scale)) {
+        if constexpr (MODE == kModeBackFixed) {
+          atomicAdd(o.acc64 + tet, (unsigned long long)__float2ll_rn(v * o.lds_scale));
+        } else if constexpr (MODE == kModeGatherFill) {
+          const int64_t p = (int64_t)atomicAdd(o.gather.cursor, 1ull);
+          gather_record(o.gather, p, tet, o.scale_exp, __float2ll_rn(v * o.lds_scale));
+        } else {
+          unsafeAtomicAdd(o.xhat + tet, v);
+        }
+      }
+    }
   } else if constexpr (MODE == kModeBackDirect) {
     if (dt > 0.f) unsafeAtomicAdd(o.xhat + tet, dt * o.weight);
   } else if constexpr (MODE == kModeCountAll) {
     o.count++;
-  } else if constexpr (MODE == kModeCountPos) {
-    if (dt > 0.f) o.count++;
   } else if constexpr (MODE == kModeTrace) {
     o.out_tet[o.cursor] = o.perm[tet];
     o.out_len[o.cursor] = dt * r.dn;
     o.cursor++;
-  } else if constexpr (MODE == kModeGatherFill) {
-    if (dt > 0.f) {
-      o.out_tet[o.cursor] = tet;
-      o.out_len[o.cursor] = dt * o.weight;
-      o.cursor += 64;  // lists interleaved by lane within the wavefront
-    }
   }
   // Keep the record one 16-byte load consumed here; otherwise the compiler
   // splits it into four loads sunk into the next step, which serialises the
@@ -466,17 +549,20 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
 }
 
 // Walk one ray from boundary face `entry` to the boundary.
-template <int MODE, class Src>
+template <int MODE, class Src, class St>
 __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, const Src& q, int entry, WalkOut<MODE>& o,
-                                         LaneStats& st) {
+                                         St& st) {
   WalkState w;
   walk_start<MODE>(M, r, q, entry, w, o);
   while (walk_step<MODE>(M, r, q, w, o, st)) {
   }
 }
 
-__device__ __forceinline__ void flush_stats(const MeshView& M, LaneStats& st, int active) {
-  // Wave-level reduction, one atomic per counter per wave.
+// Adds a wavefront's counts to the mesh's counters: a shuffle reduction of
+// the lane registers, or (LdsStats) every lane's ray and step counts added to
+// the wavefront's LDS counters; then one lane per counter adds it to global
+// memory.
+__device__ __forceinline__ void flush_stats(const MeshView& M, RegStats& st, int active) {
   int v[8] = {active, st.steps, st.zero, st.fp64, st.exact, st.pert, st.failed, st.grazing};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -489,6 +575,19 @@ __device__ __forceinline__ void flush_stats(const MeshView& M, LaneStats& st, in
 #pragma unroll
     for (int c = 0; c < 8; ++c)
       if (v[c]) atomicAdd(M.counters + c, (unsigned long long)v[c]);
+  }
+}
+
+__device__ __forceinline__ void flush_stats(const MeshView& M, LdsStats& st, int active) {
+  if (active) lds_add_u32(st.ev + kEvRays, 1u);
+  if (st.steps) lds_add_u32(st.ev + kEvSteps, (unsigned)st.steps);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int lane = threadIdx.x & 63;
+  if (lane < kEvents) {
+    const unsigned v = st.ev[lane];
+    const int slot = lane == kEvRays ? kRays : lane == kEvSteps ? kSegments : kZeroLen + lane;
+    if (v) atomicAdd(M.counters + slot, (unsigned long long)v);
   }
 }
 
@@ -519,10 +618,7 @@ struct BlockIO {
   const float* in;
   float* out_f32;
   int32_t* out_i32;
-  int64_t* counts;
-  const int64_t* offsets;
-  int32_t* keys;
-  float* vals;
+  GatherOut gather;  // kModeGatherFill
   int lds_table;
   unsigned long long* acc64;  // kModeBackFixed: fixed-point sums [nt]
   const int* scale_exp;       // kModeBackFixed: log2 of their scale
@@ -535,29 +631,34 @@ struct BlockIO {
 //   kModeBackAtomic: xhat[i] += a_ij y_j through the block's LDS table
 //   kModeBackFixed:  acc64[i] += a_ij y_j 2^scale_exp, exact integer sums
 //   kModeBackDirect: xhat[i] += a_ij y_j, one global atomic per segment
-//   kModeCountPos:   counts[wave] = 64 x the wavefront's longest list of
-//                    positive-length visits
-//   kModeGatherFill: keys/vals at offsets[wave] + 64 k + lane, padded
-// Every thread of the block must call it (the backprojection synchronises).
+//   kModeGatherFill: records of the explicit per-tetrahedron lists
+// Every thread of the block must call it.
 template <int MODE, bool kLeanSrc = false>
 __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G, const TileMap& tm, int64_t block,
                                            int a0, int na_chunk, const BlockIO& io, int* tkeys,
                                            long long* tvals) {
   int a, i, j;
   bool active = tile_ray(G, tm, block, threadIdx.x, a0, na_chunk, &a, &i, &j);
-  LaneStats st;
-  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed) {
-    __shared__ float s_wmax[4];
-    for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
-      tkeys[k] = -1;
-      tvals[k] = 0;
+  // The scatter walks keep their rare counts in LDS, the others in registers.
+  constexpr bool kTable = MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill;
+  using St = typename std::conditional<kTable, LdsStats, RegStats>::type;
+  __shared__ unsigned s_ev[kTable ? kBlockWaves * kEvents : 1];
+  St st(kTable ? wave_counters(s_ev) : nullptr);
+  if constexpr (kTable) {
+    const int lane = threadIdx.x & 63;
+    constexpr int kSlots = TableShape<MODE>::slots, kWindow = TableShape<MODE>::window;
+    lds_i32* keys = (lds_i32*)tkeys + kSlots * wave_in_block();
+    lds_i64* vals = (lds_i64*)tvals + kSlots * wave_in_block();
+    for (int k = lane; k < kSlots; k += 64) {
+      keys[k] = -1;
+      vals[k] = 0;
     }
     Ray r;
     PixelSrc q{};
     WalkOut<MODE> o;
     o.xhat = io.out_f32;
-    o.lds_keys = tkeys;
-    o.lds_vals = tvals;
+    o.lds_keys = keys;
+    o.lds_vals = vals;
     WalkState w;
     bool alive = false;
     if (active) {
@@ -571,45 +672,77 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
         alive = true;
       }
     }
-    // Fixed-point scale from the block's largest ray weight.
-    float aw = alive ? fabsf(o.weight) : 0.f;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) aw = fmaxf(aw, __shfl_xor(aw, off, 64));
-    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = aw;
-    __syncthreads();
-    const float maxw = fmaxf(fmaxf(s_wmax[0], s_wmax[1]), fmaxf(s_wmax[2], s_wmax[3]));
-    int ex = 0;
-    (void)frexpf(maxw, &ex);
-    o.lds_scale = ldexpf(1.0f, min(54 - ex, 120));
     if constexpr (MODE == kModeBackFixed) {
       // One scale for the whole launch, so that every sum is an exact
       // integer whatever the order of the additions.
       o.lds_scale = ldexpf(1.0f, *io.scale_exp);
       o.acc64 = io.acc64;
+    } else {
+      if constexpr (MODE == kModeGatherFill) o.gather = io.gather;
+      // Fixed-point scale from the wavefront's largest ray weight (a max over
+      // the float bits, which order like the values for non-negative floats).
+      __shared__ unsigned s_wmax[kBlockWaves];
+      lds_u32* wm = (lds_u32*)s_wmax + wave_in_block();
+      if (lane == 0) *wm = 0u;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (alive)
+        __hip_atomic_fetch_max(wm, __float_as_uint(fabsf(o.weight)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      int ex = 0;
+      (void)frexpf(__uint_as_float(*wm), &ex);
+      o.scale_exp = min(54 - ex, 120);
+      o.lds_scale = ldexpf(1.0f, o.scale_exp);
     }
-    const double inv_scale = 1.0 / (double)o.lds_scale;
-    // The block's rays advance together in windows of kLdsWindow steps;
-    // after each window the table is added to xhat and cleared, so it only
-    // ever holds the tetrahedra of one window of the ray bundle.
+    // The wavefront's rays advance together in windows of kWindow
+    // steps; after each window its table is added to xhat and cleared, so it
+    // only ever holds the tetrahedra of one window of the ray bundle.
     for (;;) {
 #pragma unroll 1
-      for (int k = 0; k < kLdsWindow && alive; ++k) alive = walk_step<MODE>(M, r, q, w, o, st);
-      const int any = __syncthreads_or(alive ? 1 : 0);
-      for (int k = threadIdx.x; k < kLdsSlots; k += blockDim.x) {
-        const int key = tkeys[k];
-        if (key >= 0) {
-          if constexpr (MODE == kModeBackFixed)
-            atomicAdd(io.acc64 + key, (unsigned long long)tvals[k]);
-          else
-            unsafeAtomicAdd(io.out_f32 + key, (float)((double)tvals[k] * inv_scale));
-          tkeys[k] = -1;
-          tvals[k] = 0;
+      for (int k = 0; k < kWindow && alive; ++k) alive = walk_step<MODE>(M, r, q, w, o, st);
+      // LDS operations of one wavefront complete in order: the flush sees
+      // every add of the window.
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if constexpr (MODE == kModeGatherFill) {
+        // One record per occupied slot, at consecutive positions reserved
+        // with one atomic for the wavefront.
+        unsigned total = 0;
+        for (int k = lane; k < kSlots; k += 64) total += __popcll(__ballot(keys[k] >= 0));
+        unsigned long long base = 0;
+        if (lane == 0 && total) base = atomicAdd(o.gather.cursor, (unsigned long long)total);
+        base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+               (unsigned)__builtin_amdgcn_readfirstlane((int)base);
+        for (int k = lane; k < kSlots; k += 64) {
+          const int key = keys[k];
+          const unsigned long long m = __ballot(key >= 0);
+          if (key >= 0) {
+            const int64_t p = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
+            gather_record(o.gather, p, key, o.scale_exp, vals[k]);
+            keys[k] = -1;
+            vals[k] = 0;
+          }
+          base += __popcll(m);
+        }
+      } else {
+        for (int k = lane; k < kSlots; k += 64) {
+          const int key = keys[k];
+          if (key >= 0) {
+            if constexpr (MODE == kModeBackFixed)
+              atomicAdd(io.acc64 + key, (unsigned long long)vals[k]);
+            else
+              unsafeAtomicAdd(io.out_f32 + key, (float)ldexp((double)vals[k], -ilogbf(o.lds_scale)));
+            keys[k] = -1;
+            vals[k] = 0;
+          }
         }
       }
-      __syncthreads();
-      if (!any) break;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (__ballot(alive) == 0) break;
     }
-  } else if (active && MODE != kModeCountPos && MODE != kModeGatherFill) {
+  } else if (active) {
     int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
     Ray r = cone_ray(G, M.extent, a, i, j);
     // The single-problem walks have registers to spare, so their exact paths
@@ -640,42 +773,6 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       if (e >= 0 && o.weight != 0.f) walk_ray<MODE>(M, r, q, e, o, st);
     }
   }
-  if constexpr (MODE == kModeCountPos || MODE == kModeGatherFill) {
-    // Gather lists, laid out per wavefront so that every step's stores are
-    // 64 consecutive words: segment k of lane l at base_w + 64 k + l, the
-    // wavefront taking 64 x (its longest list) slots; shorter lists are
-    // padded with key nt (sorted after every tetrahedron) and value 0.
-    // kModeCountPos writes the wavefront's slot count, kModeGatherFill the
-    // lists at the scanned bases.  Every lane of the wavefront takes part.
-    const int64_t wave = block * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    WalkOut<MODE> o;
-    if constexpr (MODE == kModeGatherFill) {
-      o.out_tet = io.keys;
-      o.out_len = io.vals;
-      o.cursor = io.offsets[wave] + lane;
-    }
-    if (active) {
-      const int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
-      const Ray r = cone_ray(G, M.extent, a, i, j);
-      const RegSrc q{r.S, r.P, r.U, r.V};
-      const int e = io.entry ? io.entry[rid] : find_entry(M, r, st);
-      if constexpr (MODE == kModeGatherFill) o.weight = io.in[rid] * r.dn;
-      if (e >= 0) walk_ray<MODE>(M, r, q, e, o, st);
-    }
-    if constexpr (MODE == kModeCountPos) {
-      int c = (int)o.count;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) c = max(c, __shfl_xor(c, off, 64));
-      if (lane == 0) io.counts[wave] = 64 * (int64_t)c;
-    } else {
-      const int64_t end = io.offsets[wave + 1];
-      for (int64_t p = o.cursor; p < end; p += 64) {
-        io.keys[p] = M.nt;
-        io.vals[p] = 0.f;
-      }
-    }
-  }
   flush_stats(M, st, active ? 1 : 0);
 }
 
@@ -686,9 +783,9 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
 template <int MODE>
 __global__ __launch_bounds__(256, 4) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
                                                          BlockIO io) {
-  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed) {
-    __shared__ int tkeys[kLdsSlots];
-    __shared__ long long tvals[kLdsSlots];
+  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
+    __shared__ int tkeys[kBlockWaves * TableShape<MODE>::slots];
+    __shared__ long long tvals[kBlockWaves * TableShape<MODE>::slots];
     walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, tkeys, tvals);
   } else {
     walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, nullptr, nullptr);
@@ -796,7 +893,7 @@ __global__ __launch_bounds__(64 * kRasterWaves) void entry_raster_kernel(MeshVie
     raster_box(G, f, make_float3(q0.x, q0.y, q0.z), make_float3(q1.x, q1.y, q1.z), make_float3(q2.x, q2.y, q2.z),
                &i0, &i1, &j0, &j1);
   }
-  LaneStats st;
+  RegStats st(nullptr);
   unsigned long long todo = __ballot(i0 <= i1 && j0 <= j1);
   while (todo) {
     const int src = __ffsll((long long)todo) - 1;
@@ -840,43 +937,46 @@ struct BatchDesc {
 
 template <int MODE>
 __global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __restrict__ D, int nprob, int64_t total,
-                                                         unsigned long long* counter,
+                                                         unsigned long long* counter, int chunk,
                                                          const float* const* __restrict__ ins,
                                                          float* const* __restrict__ outs) {
   __shared__ long long s_item;
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, (unsigned long long)chunk);
     __syncthreads();
     // The item is the same for the whole block; saying so lets the
     // descriptor below be read with scalar loads into scalar registers, as
     // kernel arguments are in the single-problem kernel.
     const long long raw = s_item;
-    const long long item = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(raw >> 32))
-                                        << 32) |
-                                       (unsigned)__builtin_amdgcn_readfirstlane((int)raw));
-    if (item >= total) break;
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (D[mid].item_begin <= item)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    const BatchDesc d = D[lo];
-    BlockIO io{};
-    io.entry = d.entry;
-    io.in = ins[d.user];
-    io.out_f32 = outs[d.user];
-    io.lds_table = d.lds_table;
-    if constexpr (MODE == kModeBackAtomic) {
-      __shared__ int tkeys[kLdsSlots];
-      __shared__ long long tvals[kLdsSlots];
-      walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
-    } else {
-      walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
+    const long long first = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(raw >> 32))
+                                         << 32) |
+                                        (unsigned)__builtin_amdgcn_readfirstlane((int)raw));
+    if (first >= total) break;
+    // `chunk` consecutive pixel blocks per fetch (they may span problems).
+    for (long long item = first; item < first + chunk && item < total; ++item) {
+      int lo = 0, hi = nprob - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (D[mid].item_begin <= item)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      lo = __builtin_amdgcn_readfirstlane(lo);
+      const BatchDesc d = D[lo];
+      BlockIO io{};
+      io.entry = d.entry;
+      io.in = ins[d.user];
+      io.out_f32 = outs[d.user];
+      io.lds_table = d.lds_table;
+      if constexpr (MODE == kModeBackAtomic) {
+        __shared__ int tkeys[kBlockWaves * TableShape<MODE>::slots];
+        __shared__ long long tvals[kBlockWaves * TableShape<MODE>::slots];
+        walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
+      } else {
+        walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
+      }
     }
   }
 }
@@ -890,7 +990,7 @@ __global__ __launch_bounds__(256) void list_walk_kernel(MeshView M, GeomView G, 
                                                         int64_t* counts, const int64_t* offsets, int32_t* tets,
                                                         float* lens) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
-  LaneStats st;
+  RegStats st(nullptr);
   bool active = k < n;
   if (active) {
     Ray r;
@@ -997,8 +1097,8 @@ int64_t pixel_walk_waves(const tct_geom* g, int na_chunk, int tile_u) {
 
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,
                              const int32_t* entry, const float* in, float* out_f32, int32_t* out_i32,
-                             int64_t* counts, const int64_t* offsets, int32_t* keys, float* vals, int tile_u,
-                             hipStream_t s, int lds_table, unsigned long long* acc64, const int* scale_exp) {
+                             const GatherOut* gather, int tile_u, hipStream_t s, int lds_table,
+                             unsigned long long* acc64, const int* scale_exp) {
   MeshView M = m->view();
   GeomView G = g->view();
   TileMap tm = make_tiles(G, tile_u);
@@ -1008,7 +1108,7 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
     set_error("too many rays in one launch");
     return TCT_E_ARG;
   }
-  BlockIO io{entry, in, out_f32, out_i32, counts, offsets, keys, vals, lds_table, acc64, scale_exp};
+  BlockIO io{entry, in, out_f32, out_i32, gather ? *gather : GatherOut{}, lds_table, acc64, scale_exp};
   dim3 grid((unsigned)blocks), block(256);
 #define TCT_LAUNCH(MODE_) \
   hipLaunchKernelGGL(pixel_walk_kernel<MODE_>, grid, block, 0, s, M, G, tm, a0, na_chunk, io)
@@ -1030,9 +1130,6 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
       break;
     case kModeBackFixed:
       TCT_LAUNCH(kModeBackFixed);
-      break;
-    case kModeCountPos:
-      TCT_LAUNCH(kModeCountPos);
       break;
     case kModeGatherFill:
       TCT_LAUNCH(kModeGatherFill);
@@ -1077,8 +1174,8 @@ tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float*
     tct_status st = launch_fill(xhat, m->nt, 0.f, s);
     if (st != TCT_OK) return st;
   }
-  return launch_pixel_walk(kModeBackAtomic, m, g, 0, g->na, entry, proj, xhat, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, tile_u, s, lds_table);
+  return launch_pixel_walk(kModeBackAtomic, m, g, 0, g->na, entry, proj, xhat, nullptr, nullptr, tile_u, s,
+                           lds_table);
 }
 
 // Reproducible scatter (TCT_BP_FIXED).  Every term L y_j |d_j| is rounded
@@ -1130,8 +1227,8 @@ static tct_status backproject_fixed_in(const tct_mesh* m, const tct_geom* g, con
   hipError_t e = hipGetLastError();
   tct_status st = TCT_OK;
   if (e == hipSuccess)
-    st = launch_pixel_walk(kModeBackFixed, m, g, a_begin, a_count, entry, proj, xhat, nullptr, nullptr, nullptr,
-                           nullptr, nullptr, tile_u, s, 1, acc, scale_exp);
+    st = launch_pixel_walk(kModeBackFixed, m, g, a_begin, a_count, entry, proj, xhat, nullptr, nullptr, tile_u,
+                           s, 1, acc, scale_exp);
   if (e == hipSuccess && st == TCT_OK) {
     hipLaunchKernelGGL(fixed_finish_kernel, dim3((unsigned)((m->nt + 255) / 256)), dim3(256), 0, s,
                        (const unsigned long long*)acc, (const int*)scale_exp, xhat, m->nt, accumulate);
@@ -1291,10 +1388,10 @@ tct_status batch_walk(tct_batch* b, int mode, const tct_vecset* in, const tct_ve
   const BatchDesc* D = (const BatchDesc*)b->d_desc;
   if (mode == kModeForward) {
     hipLaunchKernelGGL(batch_walk_kernel<kModeForward>, dim3(b->grid_fwd), dim3(256), 0, s, D, b->n, b->total_items,
-                       b->d_counter, (const float* const*)in->d_ptrs, out->d_ptrs);
+                       b->d_counter, b->queue_chunk, (const float* const*)in->d_ptrs, out->d_ptrs);
   } else if (mode == kModeBackAtomic) {
     hipLaunchKernelGGL(batch_walk_kernel<kModeBackAtomic>, dim3(b->grid_bwd), dim3(256), 0, s, D, b->n,
-                       b->total_items, b->d_counter, (const float* const*)in->d_ptrs, out->d_ptrs);
+                       b->total_items, b->d_counter, b->queue_chunk, (const float* const*)in->d_ptrs, out->d_ptrs);
   } else {
     set_error("batch_walk: unsupported mode");
     return TCT_E_ARG;

@@ -161,3 +161,36 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path):
         cached = json.load(f)
     assert len(cached) == 1
     assert tct.autotune.tune(P, cache_path=path) == res
+
+
+def test_batch_autotune_tiles_and_queue_chunk_then_same_results():
+    """The batch tuner times tiles per problem and the queue chunk on the
+    persistent batched kernel itself; whatever it picks, the batched forward
+    equals the plain one bit for bit and the batched backprojection matches
+    the plain scatter."""
+    tct = _tct()
+    probs = problems()
+    Ps = [P for _, P in probs]
+    tuned = tct.autotune.tune_batch(Ps, n_angles=2, reps=1)
+    assert len(tuned["tile_u"]) == len(Ps) and all(t in (4, 8, 16, 32, 64) for t in tuned["tile_u"])
+    assert tuned["queue_chunk"] in (1, 2, 4, 8)
+    assert set(tuned["queue_ms"]) == {"1", "2", "4", "8"}
+    B = tct.BatchProjector(Ps, tuned["tile_u"])
+    B.set_queue_chunk(tuned["queue_chunk"])
+    xs = [P.mesh.to_internal(torch.as_tensor(w.x, device=DEV)) for w, P in probs]
+    outs = [torch.empty(P.geom.nrays, device=DEV) for P in Ps]
+    B.forward(tct.VecSet(xs), tct.VecSet(outs))
+    for P, x, o in zip(Ps, xs, outs):
+        assert torch.equal(o, P.forward(x).reshape(-1))
+    ys = [torch.rand(P.geom.nrays, device=DEV) for P in Ps]
+    xh = [torch.empty(P.nt, device=DEV) for P in Ps]
+    for c in (1, 3, 64):
+        B.set_queue_chunk(c)
+        B.backproject(tct.VecSet(ys), tct.VecSet(xh))
+        for P, y, got in zip(Ps, ys, xh):
+            ref = P.backproject(y)
+            assert torch.allclose(got, ref, rtol=1e-5, atol=1e-6 * float(ref.abs().max())), c
+    with pytest.raises(tct._lib.TctError):
+        B.set_queue_chunk(0)
+    for P in Ps:
+        assert P.mesh.stats(reset=True)["failed"] == 0

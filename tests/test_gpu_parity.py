@@ -637,3 +637,33 @@ def test_walk_failure_is_counted_and_reported():
     assert st.failed == 2 and st.rays == 4
     assert lib().tct_stats_read(m.handle, ctypes.byref(st), 0) == 0
     assert st.failed == 0
+
+
+@pytest.mark.parametrize("shape", ["sparse_rays", "long_lists"])
+def test_gather_record_buffer_regrowth_and_long_lists(shape):
+    """Explicit per-tetrahedron lists at their edges: a coarse detector on a
+    fine mesh (few rays per wavefront, so nearly every segment is a record of
+    its own: the record buffer sized from a guess overflows and the chunk is
+    walked again with room for all), and a tiny mesh under a large detector
+    (thousands of records per tetrahedron, beyond the in-LDS sort).  Both
+    within the bars of the oracle and the same bits twice."""
+    tct = _gpu()
+    if shape == "sparse_rays":
+        w = synth.jittered_kuhn(24, 41, 42, 5, 4, 6)
+        w.cone = synth.Cone(4.0, 8.0, 5, 4, 0.37, 0.41, 0.01, 0.02)
+    else:
+        w = synth.jittered_kuhn(2, 43, 44, 192, 160, 24)
+    orc = oracle.Oracle(w.verts, w.tets, w.cone, w.angles)
+    mesh = tct.TetMesh(w.verts, w.tets, device=DEV)
+    geom = tct.ConeGeometry(w.cone, w.angles, device=DEV)
+    P = tct.Projector(mesh, geom)
+    H = element_size(w.verts, w.tets, orc.mesh.tables()[1])
+    y = np.random.default_rng(45).uniform(-1, 1, orc.nrays).astype(f32)
+    ref, tol = backprojection_reference(orc, y, H)
+    yt = torch.as_tensor(y, device=DEV)
+    a = P.backproject(yt, mode="gather")
+    b = P.backproject(yt, mode="gather")
+    assert torch.equal(a, b)
+    got = mesh.to_user(a).cpu().numpy().astype(np.float64)
+    assert_within(got, ref, tol, f"{shape} gather backprojection")
+    assert mesh.stats(reset=True)["failed"] == 0
