@@ -410,7 +410,9 @@ tct_status tct_vecset_fill(const tct_vecset* y, float value, tct_stream s);
 
 /* A batch of n (mesh, geometry) problems on one device.  tile_u: host int32 [n]
  * wavefront tile widths (NULL = 8).  entries: host array of n device entry
- * caches from tct_entry (NULL, or NULL elements, = search in-kernel).  The
+ * caches from tct_entry / tct_entry_raster; for NULL (or NULL elements) the
+ * batch computes its own caches by boundary projection (device memory it
+ * frees in tct_batch_destroy; synchronises the device).  The
  * handles must outlive the batch.  A batch is stream-exclusive: its work
  * counter is reset by each call. */
 tct_status tct_batch_create(const tct_mesh* const* meshes, const tct_geom* const* geoms, int32_t n,

@@ -11,6 +11,10 @@
 
 #include "../../include/tetct.h"
 
+#ifndef TCT_XCD_REMAP
+#define TCT_XCD_REMAP 1
+#endif
+
 namespace tct {
 
 // One bounding-volume-hierarchy node over boundary faces, 32 bytes, stored
@@ -83,6 +87,25 @@ enum Counter {
   kGrazing,
   kNumCounters = 8
 };
+
+// XCD-aware block order.  The chip's 256 compute units sit in 8 dies
+// (XCDs), each with its own L2, and the dispatcher hands workgroup b to die
+// b mod 8.  Launches whose neighbouring blocks share data renumber their
+// blocks so that each die takes one contiguous run of the logical order
+// instead of every eighth block: die x (0..7) processes logical blocks
+// [x per + min(x, rem), ...) with per = n / 8 and rem = n mod 8, the first
+// rem dies one block more.  A bijection on [0, n) for any n.
+constexpr int kXcds = 8;
+__host__ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
+#if TCT_XCD_REMAP
+  const int64_t per = n / kXcds, rem = n % kXcds;
+  const int64_t x = b % kXcds, i = b / kXcds;
+  return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+#else
+  (void)n;
+  return b;
+#endif
+}
 
 void set_error(const std::string& msg);
 tct_status hip_fail(hipError_t e, const char* what);
@@ -161,6 +184,7 @@ struct tct_batch {
   unsigned long long* d_counter = nullptr;
   int grid_fwd = 0, grid_bwd = 0;  // persistent grid sizes
   int queue_chunk = 1;             // pixel blocks handed out per queue fetch
+  std::vector<int32_t*> owned_entries;  // entry caches made for problems given without one
 };
 
 struct tct_geom {

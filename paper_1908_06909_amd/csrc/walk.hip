@@ -406,12 +406,17 @@ struct WalkState {
   double s_in;  // ray parameter where the ray entered the current tetrahedron
   float xcur;  // forward projection: x of the current tetrahedron
   int steps;
+  // Every ray of the wavefront ends beyond the mesh (ends_beyond_mesh), so
+  // segments need no clamp at the end point; the same for the whole
+  // wavefront, hence a scalar branch per step.
+  bool far;
 };
 
 // Enter the mesh through boundary face `entry`.
 template <int MODE, class Src>
 __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, const Src& q, int entry, WalkState& w,
-                                           const WalkOut<MODE>& o) {
+                                           const WalkOut<MODE>& o, bool far) {
+  w.far = far;
   const float4* bq = M.bfaces + 4 * (size_t)entry;
   float4 q0 = bq[0], q1 = bq[1], q2 = bq[2], q3 = bq[3];
   w.tet = __float_as_int(q0.w);
@@ -454,9 +459,9 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   // case; otherwise each edge gets its own bound before any float64 work.
   int k = step_exit_common(g);
   if (k < 0) {
-    int s0 = step_edge_certified(g.E0, g.l0, g.K);
-    int s1 = step_edge_certified(g.E1, g.l1, g.K);
-    int s2 = step_edge_certified(g.E2, g.l2, g.K);
+    int s0 = step_edge_certified(g.E0, g.m0, g.K);
+    int s1 = step_edge_certified(g.E1, g.m1, g.K);
+    int s2 = step_edge_certified(g.E2, g.m2, g.K);
     if (s0 == 0) s0 = resolve_src(q, v, w.a0, st);
     if (s1 == 0) s1 = resolve_src(q, v, w.a1, st);
     if (s2 == 0) s2 = resolve_src(q, v, w.a2, st);
@@ -476,7 +481,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   float3 n = f3cross(ei, ej);
   float den = f3dot(r.d, n);
   float dt;
-  if (den * den >= r.gdd * f3dot(n, n)) {
+  if (fabsf(den) > r.gd * fmaxf(fabsf(n.x), fmaxf(fabsf(n.y), fabsf(n.z)))) {
     dt = f3dot(D, n) * __builtin_amdgcn_rcpf(den);  // v_rcp_f32, about 1 ulp
   } else {
     st.add_grazing();
@@ -486,7 +491,10 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
                                   k2 ? w.a1.z : (k0 ? w.a2.z : w.a0.z));
     dt = (float)(crossing_s_fp64(q.S(), q.P(), v, ai, aj) - w.s_in);
   }
-  dt = __builtin_amdgcn_fmed3f(dt, 0.0f, (float)fmax(0.5 - w.s_in, 0.0));
+  if (w.far)  // (1, the whole ray's parameter range, is an inline constant)
+    dt = __builtin_amdgcn_fmed3f(dt, 0.0f, 1.0f);
+  else
+    dt = __builtin_amdgcn_fmed3f(dt, 0.0f, (float)fmax(0.5 - w.s_in, 0.0));
   if (dt == 0.f) st.add_zero();
   // Next tetrahedron across the exit face (local face index loc[k]).
   const int tet = w.tet;
@@ -553,7 +561,8 @@ template <int MODE, class Src, class St>
 __device__ __forceinline__ void walk_ray(const MeshView& M, const Ray& r, const Src& q, int entry, WalkOut<MODE>& o,
                                          St& st) {
   WalkState w;
-  walk_start<MODE>(M, r, q, entry, w, o);
+  // Called by the lanes that walk: the vote is over them.
+  walk_start<MODE>(M, r, q, entry, w, o, __all(ends_beyond_mesh(r, M.extent)) != 0);
   while (walk_step<MODE>(M, r, q, w, o, st)) {
   }
 }
@@ -633,7 +642,9 @@ struct BlockIO {
 //   kModeBackDirect: xhat[i] += a_ij y_j, one global atomic per segment
 //   kModeGatherFill: records of the explicit per-tetrahedron lists
 // Every thread of the block must call it.
-template <int MODE, bool kLeanSrc = false>
+// kCached: every ray's entry face comes from io.entry (the launch has an
+// entry cache), so the kernel carries no tree search.
+template <int MODE, bool kLeanSrc = false, bool kCached = false>
 __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G, const TileMap& tm, int64_t block,
                                            int a0, int na_chunk, const BlockIO& io, int* tkeys,
                                            long long* tvals) {
@@ -661,17 +672,24 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     o.lds_vals = vals;
     WalkState w;
     bool alive = false;
+    bool ends_far = true;
     if (active) {
       int64_t rid = ((int64_t)a * G.nv + j) * G.nu + i;
       r = cone_ray(G, M.extent, a, i, j);
       q = pixel_src(G, a, i, j);
-      int e = io.entry ? io.entry[rid] : find_entry(M, r, st);
+      ends_far = ends_beyond_mesh(r, M.extent);
+      int e;
+      if constexpr (kCached)
+        e = io.entry[rid];
+      else
+        e = io.entry ? io.entry[rid] : find_entry(M, r, st);
       o.weight = io.in[rid] * r.dn;
       if (e >= 0 && o.weight != 0.f) {
-        walk_start<MODE>(M, r, q, e, w, o);
+        walk_start<MODE>(M, r, q, e, w, o, false);
         alive = true;
       }
     }
+    w.far = __all(ends_far) != 0;
     if constexpr (MODE == kModeBackFixed) {
       // One scale for the whole launch, so that every sum is an exact
       // integer whatever the order of the additions.
@@ -757,6 +775,8 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     int e;
     if constexpr (MODE == kModeEntryRstar)
       e = find_entry<true>(M, r, st);
+    else if constexpr (kCached && MODE != kModeEntry)
+      e = io.entry[rid];
     else
       e = (io.entry && MODE != kModeEntry) ? io.entry[rid] : find_entry(M, r, st);
     if constexpr (MODE == kModeEntry || MODE == kModeEntryRstar) {
@@ -780,15 +800,16 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
 
 // ---------------------------------------------------------------- kernels
 
-template <int MODE>
+template <int MODE, bool kCached>
 __global__ __launch_bounds__(256, 4) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
                                                          BlockIO io) {
   if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
     __shared__ int tkeys[kBlockWaves * TableShape<MODE>::slots];
     __shared__ long long tvals[kBlockWaves * TableShape<MODE>::slots];
-    walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, tkeys, tvals);
+    walk_block<MODE, false, kCached>(M, G, tm, xcd_block(blockIdx.x, gridDim.x), a0, na_chunk, io, tkeys, tvals);
   } else {
-    walk_block<MODE>(M, G, tm, blockIdx.x, a0, na_chunk, io, nullptr, nullptr);
+    walk_block<MODE, false, kCached>(M, G, tm, xcd_block(blockIdx.x, gridDim.x), a0, na_chunk, io, nullptr,
+                                     nullptr);
   }
 }
 
@@ -973,9 +994,9 @@ __global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __r
       if constexpr (MODE == kModeBackAtomic) {
         __shared__ int tkeys[kBlockWaves * TableShape<MODE>::slots];
         __shared__ long long tvals[kBlockWaves * TableShape<MODE>::slots];
-        walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
+        walk_block<MODE, true, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
       } else {
-        walk_block<MODE, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
+        walk_block<MODE, true, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
       }
     }
   }
@@ -1110,14 +1131,19 @@ tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int
   }
   BlockIO io{entry, in, out_f32, out_i32, gather ? *gather : GatherOut{}, lds_table, acc64, scale_exp};
   dim3 grid((unsigned)blocks), block(256);
-#define TCT_LAUNCH(MODE_) \
-  hipLaunchKernelGGL(pixel_walk_kernel<MODE_>, grid, block, 0, s, M, G, tm, a0, na_chunk, io)
+#define TCT_LAUNCH(MODE_)                                                                              \
+  do {                                                                                                 \
+    if (entry)                                                                                         \
+      hipLaunchKernelGGL((pixel_walk_kernel<MODE_, true>), grid, block, 0, s, M, G, tm, a0, na_chunk, io);  \
+    else                                                                                               \
+      hipLaunchKernelGGL((pixel_walk_kernel<MODE_, false>), grid, block, 0, s, M, G, tm, a0, na_chunk, io); \
+  } while (0)
   switch (mode) {
     case kModeEntry:
-      TCT_LAUNCH(kModeEntry);
+      hipLaunchKernelGGL((pixel_walk_kernel<kModeEntry, false>), grid, block, 0, s, M, G, tm, a0, na_chunk, io);
       break;
     case kModeEntryRstar:
-      TCT_LAUNCH(kModeEntryRstar);
+      hipLaunchKernelGGL((pixel_walk_kernel<kModeEntryRstar, false>), grid, block, 0, s, M, G, tm, a0, na_chunk, io);
       break;
     case kModeForward:
       TCT_LAUNCH(kModeForward);
@@ -1356,6 +1382,24 @@ tct_status batch_build(const tct_mesh* const* meshes, const tct_geom* const* geo
     return hip_fail(e, what);
   };
   hipError_t e;
+  // The batched kernels read every entry face from a cache: problems given
+  // without one get a batch-owned cache, filled here by boundary projection.
+  for (int k = 0; k < n; ++k) {
+    if (sorted[k].entry) continue;
+    const int p = sorted[k].user;
+    const int64_t nrays = (int64_t)geoms[p]->na * geoms[p]->cone.nu * geoms[p]->cone.nv;
+    int32_t* cache = nullptr;
+    if ((e = hipMalloc((void**)&cache, sizeof(int32_t) * (size_t)std::max<int64_t>(1, nrays))) != hipSuccess)
+      return fail(e, "hipMalloc(batch entry cache)");
+    b->owned_entries.push_back(cache);
+    const tct_status st = entry_raster(meshes[p], geoms[p], cache, nullptr);
+    if (st != TCT_OK) {
+      batch_free(b);
+      return st;
+    }
+    sorted[k].entry = cache;
+  }
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return fail(e, "batch entry caches");
   if ((e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * (size_t)n)) != hipSuccess) return fail(e, "hipMalloc(batch)");
   if ((e = hipMemcpy(b->d_desc, sorted.data(), sizeof(BatchDesc) * (size_t)n, hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e, "hipMemcpy(batch)");
@@ -1380,6 +1424,7 @@ void batch_free(tct_batch* b) {
   if (!b) return;
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  for (int32_t* p : b->owned_entries) (void)hipFree(p);
   delete b;
 }
 

@@ -40,19 +40,22 @@ constexpr float kFilterAbs = 7.888609052210118e-31f;  // 2^-100
 // E(v, a) = (a - v) . (d x (v - S)) = (a - v) . (d x (v - Q)) differs from
 // fl(e . w) by at most |e|_1 |d|_inf (20.5 u |D|_inf + 57.2 u^2 R): six
 // roundings per monomial of e.(d_hi x D), the d_lo x D term, and the error of
-// D itself.  The constants below (24 u, 64 u^2) leave room for the rounding of
-// the bound's own evaluation.
-constexpr float kWalkRel = 24.0f * 5.9604644775390625e-8f * TCT_FILTER_BOUND_SCALE;
-constexpr float kWalkAbs2 = 64.0f * 3.552713678800501e-15f * TCT_FILTER_BOUND_SCALE;  // 64 u^2
+// D itself.  The step measures edges by |e|_inf (one max of magnitudes, no
+// rounding) and |e|_1 <= 3 |e|_inf, so the constants carry a factor 3:
+// 72 u = 3 x 24 u and 192 u^2 = 3 x 64 u^2, where 24 u and 64 u^2 leave room
+// for the rounding of the bound's own evaluation.
+constexpr float kWalkRel = 72.0f * 5.9604644775390625e-8f * TCT_FILTER_BOUND_SCALE;
+constexpr float kWalkAbs2 = 192.0f * 3.552713678800501e-15f * TCT_FILTER_BOUND_SCALE;  // 192 u^2
 
-// cos^2 of the angle between the ray and a face normal below which the
-// crossing is recomputed in float64.  With the vertex offset D accurate to a
-// few ulps of |D| (offset_from_ray), the float32 crossing moves by about
-// c u h / cos (h the face diameter, c ~ 5 from the rounded normal), i.e.
-// 4e-5 h at cos = 1/128; about one segment in ten thousand is that oblique,
-// so the bound on a projection, a sum over some hundred segments, stays near
-// 1e-7 of it.
-constexpr float kGrazingCos2 = 1.0f / 16384.0f;
+// The crossing is recomputed in float64 when |d . n| < sqrt(3) |d| |n|_inf /
+// 128, which takes in every face whose normal makes cos < 1/128 with the ray
+// (|n|_2 <= sqrt(3) |n|_inf) and at most sqrt(3) times that angle.  With the
+// vertex offset D accurate to a few ulps of |D| (offset_from_ray), the
+// float32 crossing moves by about c u h / cos (h the face diameter, c ~ 5
+// from the rounded normal), i.e. 4e-5 h at cos = 1/128; well under one
+// segment in ten thousand is that oblique, so the bound on a projection, a
+// sum over some hundred segments, stays near 1e-7 of it.
+constexpr float kGrazingBound = 1.7320509f / 128.0f;
 
 // The ray leaves through the face (v, a_{k+1}, a_{k+2}) opposite entry slot
 // k (indices mod 3) for which E(v, a_{k+1}) < 0 < E(v, a_{k+2}), the first of
@@ -68,9 +71,9 @@ struct Ray {
   double dx64, dy64, dz64;  // P - S (exact in float64)
   double Mx64, My64, Mz64;  // the ray point at t = 1/2
   float dn;    // |d| (Euclidean)
-  float gdd;   // |d|^2 / 16384 (grazing test)
-  float kA;    // |d|_inf 24 u        walk filter: K = kA |D|_inf + kB
-  float kB;    // |d|_inf 64 u^2 R, R bounding every coordinate met on this ray
+  float gd;    // sqrt(3) |d| / 128 (grazing test)
+  float kA;    // |d|_inf 72 u        walk filter: K = kA |D|_inf + kB
+  float kB;    // |d|_inf 192 u^2 R, R bounding every coordinate met on this ray
 };
 
 // The ray is carried with d_hi = fl(P - S) for the float32 filters and, in
@@ -89,13 +92,25 @@ __host__ __device__ __forceinline__ void finish_ray(Ray& r, float mesh_extent) {
   r.ad = f3abs(r.d);
   const float dd = r.d.x * r.d.x + r.d.y * r.d.y + r.d.z * r.d.z;
   r.dn = sqrtf(dd);
-  r.gdd = kGrazingCos2 * dd;  // exact: a power of two
+  r.gd = kGrazingBound * r.dn;
   const float dinf = fmaxf(r.ad.x, fmaxf(r.ad.y, r.ad.z));
   float sp = fmaxf(fmaxf(fmaxf(fabsf(r.S.x), fabsf(r.S.y)), fmaxf(fabsf(r.S.z), fabsf(r.P.x))),
                    fmaxf(fabsf(r.P.y), fabsf(r.P.z)));
   float R = (fmaxf(sp, mesh_extent) + dinf) * 1.0001f;
   r.kA = dinf * kWalkRel;
-  r.kB = dinf * (kWalkAbs2 * R);  // |d|_inf 64 u^2 R with u = 2^-24
+  r.kB = dinf * (kWalkAbs2 * R);  // |d|_inf 192 u^2 R with u = 2^-24
+}
+
+// True when every point of the cube [-extent, extent]^3, which holds the
+// mesh, lies before the ray's end point P by more than 2^-10 of the ray
+// parameter: max over the cube of (X - P).d = extent |d|_1 - P.d.  A walk
+// inside the mesh then never reaches t = 1, and its segments need no clamp
+// at the end point.  Float64 from the exact direction.
+__host__ __device__ __forceinline__ bool ends_beyond_mesh(const Ray& r, float extent) {
+  const double d1 = fabs(r.dx64) + fabs(r.dy64) + fabs(r.dz64);
+  const double dd = r.dx64 * r.dx64 + r.dy64 * r.dy64 + r.dz64 * r.dz64;
+  const double pd = (double)r.P.x * r.dx64 + (double)r.P.y * r.dy64 + (double)r.P.z * r.dz64;
+  return pd - (double)extent * d1 > 0x1p-10 * dd;
 }
 
 // D = v - Q for the ray point Q = M + s d, in float64: M, v - M and the
@@ -138,8 +153,8 @@ struct StepEdges {
   float3 D;           // v - Q, rounded to float32
   float3 e0, e1, e2;  // a_k - v
   float E0, E1, E2;   // float32 estimates of E(v, a_k)
-  float l0, l1, l2;   // |e_k|_1
-  float K;            // |d|_inf (24 u |D|_inf + 64 u^2 R): per-unit-length bound
+  float m0, m1, m2;   // |e_k|_inf
+  float K;            // |d|_inf (72 u |D|_inf + 192 u^2 R): bound per unit of |e|_inf
 };
 
 __host__ __device__ __forceinline__ void step_edges(const Ray& r, double s, float3 v, float3 a0, float3 a1, float3 a2,
@@ -153,16 +168,16 @@ __host__ __device__ __forceinline__ void step_edges(const Ray& r, double s, floa
   g.E0 = f3dot(g.e0, wv);
   g.E1 = f3dot(g.e1, wv);
   g.E2 = f3dot(g.e2, wv);
-  g.l0 = fabsf(g.e0.x) + fabsf(g.e0.y) + fabsf(g.e0.z);
-  g.l1 = fabsf(g.e1.x) + fabsf(g.e1.y) + fabsf(g.e1.z);
-  g.l2 = fabsf(g.e2.x) + fabsf(g.e2.y) + fabsf(g.e2.z);
+  g.m0 = fmaxf(fabsf(g.e0.x), fmaxf(fabsf(g.e0.y), fabsf(g.e0.z)));
+  g.m1 = fmaxf(fabsf(g.e1.x), fmaxf(fabsf(g.e1.y), fabsf(g.e1.z)));
+  g.m2 = fmaxf(fabsf(g.e2.x), fmaxf(fabsf(g.e2.y), fabsf(g.e2.z)));
 }
 
 // One bound from the longest edge settles all three signs in the common
 // case: returns the exit slot (0..2; 3 when all three signs agree, a failed
 // walk), or -1 when some sign is uncertain under that bound.
 __host__ __device__ __forceinline__ int step_exit_common(const StepEdges& g) {
-  if (fminf(fabsf(g.E0), fminf(fabsf(g.E1), fabsf(g.E2))) > fmaf(fmaxf(g.l0, fmaxf(g.l1, g.l2)), g.K, kFilterAbs)) {
+  if (fminf(fabsf(g.E0), fminf(fabsf(g.E1), fabsf(g.E2))) > fmaf(fmaxf(g.m0, fmaxf(g.m1, g.m2)), g.K, kFilterAbs)) {
     const unsigned n = (__builtin_bit_cast(unsigned, g.E0) >> 31) | ((__builtin_bit_cast(unsigned, g.E1) >> 31) << 1) |
                        ((__builtin_bit_cast(unsigned, g.E2) >> 31) << 2);
     return (int)((kExitFace >> (2 * n)) & 3u);
@@ -171,8 +186,8 @@ __host__ __device__ __forceinline__ int step_exit_common(const StepEdges& g) {
 }
 
 // Each edge under its own bound: 1 / -1 when certain, 0 when not.
-__host__ __device__ __forceinline__ int step_edge_certified(float E, float l, float K) {
-  return fabsf(E) - fmaf(l, K, kFilterAbs) > 0.f ? (E > 0.f ? 1 : -1) : 0;
+__host__ __device__ __forceinline__ int step_edge_certified(float E, float m, float K) {
+  return fabsf(E) - fmaf(m, K, kFilterAbs) > 0.f ? (E > 0.f ? 1 : -1) : 0;
 }
 
 // Exit slot from three decided signs (same rule as the table).

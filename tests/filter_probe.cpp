@@ -34,9 +34,9 @@ void probe_step(long long n, const float* S, const float* P, const float* extent
     StepEdges g;
     step_edges(r, s[k], f3(v + 3 * k), f3(a0 + 3 * k), f3(a1 + 3 * k), f3(a2 + 3 * k), g);
     common[k] = step_exit_common(g);
-    edge[3 * k + 0] = step_edge_certified(g.E0, g.l0, g.K);
-    edge[3 * k + 1] = step_edge_certified(g.E1, g.l1, g.K);
-    edge[3 * k + 2] = step_edge_certified(g.E2, g.l2, g.K);
+    edge[3 * k + 0] = step_edge_certified(g.E0, g.m0, g.K);
+    edge[3 * k + 1] = step_edge_certified(g.E1, g.m1, g.K);
+    edge[3 * k + 2] = step_edge_certified(g.E2, g.m2, g.K);
     const float E[3] = {g.E0, g.E1, g.E2};
     for (int i = 0; i < 3; ++i) fsign[3 * k + i] = E[i] > 0.f ? 1 : (E[i] < 0.f ? -1 : 0);
   }
@@ -52,7 +52,7 @@ void probe_entry(long long n, const float* S, const float* P, const float* exten
 }
 
 // Offsets D = v - Q of the walk (offset_from_ray), and the ray's R bound
-// as finish_ray forms it (kB / (|d|_inf 64 u^2)).
+// as finish_ray forms it (kB / (|d|_inf 192 u^2)).
 void probe_offset(long long n, const float* S, const float* P, const float* extent, const double* s, const float* v,
                   float* D, float* kA, float* kB) {
   for (long long k = 0; k < n; ++k) {
@@ -73,3 +73,6 @@ int probe_exit_table(int n_neg_bits) {
   return table == exit_slot(s0, s1, s2) ? table : -100 - table;
 }
 }
+
+// XCD-aware block order (common.h) for one launch of n blocks.
+extern "C" long long probe_xcd_block(long long b, long long n) { return (long long)xcd_block(b, n); }

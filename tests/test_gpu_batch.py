@@ -154,7 +154,7 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path):
     tct = _tct()
     w, P = problems()[5]
     path = os.path.join(str(tmp_path), "tune.json")
-    res = tct.autotune.tune(P, n_angles=2, reps=1, cache_path=path)
+    res = tct.autotune.tune(P, n_angles=2, reps=1, cache_path=path, min_rays=0)
     assert res["tile_u"] in (4, 8, 16, 32, 64)
     assert set(res["ms"]) == {"4", "8", "16", "32", "64"}
     with open(path) as f:
@@ -171,7 +171,7 @@ def test_batch_autotune_tiles_and_queue_chunk_then_same_results():
     tct = _tct()
     probs = problems()
     Ps = [P for _, P in probs]
-    tuned = tct.autotune.tune_batch(Ps, n_angles=2, reps=1)
+    tuned = tct.autotune.tune_batch(Ps, n_angles=2, reps=1, min_rays=0)
     assert len(tuned["tile_u"]) == len(Ps) and all(t in (4, 8, 16, 32, 64) for t in tuned["tile_u"])
     assert tuned["queue_chunk"] in (1, 2, 4, 8)
     assert set(tuned["queue_ms"]) == {"1", "2", "4", "8"}

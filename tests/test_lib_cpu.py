@@ -168,3 +168,22 @@ def test_null_arguments_are_rejected():
     assert L.tct_mesh_counts(None, None, None, None, None) == -1
     assert L.tct_stats_read(None, None, 0) == -1
     assert L.tct_backproject(None, None, None, None, 0, 0, None, None) == -1
+
+
+def test_autotune_host_rules():
+    """The tuner's choice rules: the default stays unless a candidate beats it
+    by more than the margin; timing subsets hold at least min_rays rays."""
+    from types import SimpleNamespace
+
+    from paper_1908_06909_amd import autotune
+
+    assert autotune._pick({4: 1.00, 8: 1.02, 16: 1.5}, 8, 0.03) == 8
+    assert autotune._pick({4: 0.90, 8: 1.00, 16: 1.5}, 8, 0.03) == 4
+    assert autotune._pick({1: 1.0, 2: 0.5}, 8, 0.03) == 2  # default not among the candidates
+    P = SimpleNamespace(geom=SimpleNamespace(nu=128, nv=128, na=64))
+    assert autotune.subset_angles(P, 4, 0) == 4
+    assert autotune.subset_angles(P, 4, 1 << 21) == 64  # capped at all angles
+    P.geom.na = 720
+    assert autotune.subset_angles(P, 4, 1 << 21) == 128
+    P.geom.nu = P.geom.nv = 512
+    assert autotune.subset_angles(P, 4, 1 << 21) == 8

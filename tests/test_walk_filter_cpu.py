@@ -5,8 +5,8 @@ signs E(v, a) = det[P - S, v - S, a - S] (Section II-C: the sign decisions
 that must not fail on rays through vertices and edges).  The kernels take a
 float32 estimate whenever a certified error bound says its sign is right and
 hand everything else to float64 and exact arithmetic.  The certification
-rests on hand-derived constants (walk_filter.h: 24 u and 64 u^2 R for the
-step, 10 u for the entry test, the error of the float64 offset from the
+rests on hand-derived constants (walk_filter.h: 72 u and 192 u^2 R per unit
+of |e|_inf for the step, 10 u for the entry test, the error of the float64 offset from the
 ray).  These tests compile that header for the host (tests/filter_probe.cpp)
 and check, over a million adversarial inputs, that every sign it certifies
 equals the exact sign the oracle computes:
@@ -45,8 +45,8 @@ def _build_probe(tag, extra):
     os.makedirs(BUILD, exist_ok=True)
     out = os.path.join(BUILD, f"libfilter_probe{tag}.so")
     src = os.path.join(HERE, "filter_probe.cpp")
-    hdr = os.path.join(ROOT, "paper_1908_06909_amd", "csrc", "walk_filter.h")
-    if not os.path.exists(out) or os.path.getmtime(out) < max(os.path.getmtime(src), os.path.getmtime(hdr)):
+    hdrs = [os.path.join(ROOT, "paper_1908_06909_amd", "csrc", h) for h in ("walk_filter.h", "common.h")]
+    if not os.path.exists(out) or os.path.getmtime(out) < max(os.path.getmtime(f) for f in [src, *hdrs]):
         cmd = [os.environ.get("HIPCC", "/opt/rocm/bin/hipcc"), "-x", "hip", "--offload-arch=gfx950", "-O2",
                "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fno-gpu-rdc",
                "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "paper_1908_06909_amd", "csrc"),
@@ -65,6 +65,8 @@ def _build_probe(tag, extra):
     L.probe_offset.argtypes = [C.c_longlong, f3, f3, f3, f8, f3, f3, f3, f3]
     L.probe_offset.restype = None
     L.probe_exit_table.argtypes = [C.c_int]
+    L.probe_xcd_block.argtypes = [C.c_longlong, C.c_longlong]
+    L.probe_xcd_block.restype = C.c_longlong
     return L
 
 
@@ -183,7 +185,7 @@ def base_steps():
     parts.append(_pixel_steps(synth.Workload("delaunay", dv, dt, synth.uniform_random(len(dt), 2),
                                              synth.Cone(4.0, 8.0, 40, 40, 0.05, 0.05, 0.003, -0.002),
                                              synth.angles_for(5)), 1, rng))
-    # a source 2^12 away: the 64 u^2 R term of the walk bound
+    # a source 2^12 away: the 192 u^2 R term of the walk bound
     far = synth.plain_kuhn(8, 0, 48, 48, 6, pitch=2.0 ** -5)
     far.cone = synth.Cone(4096.0, 8192.0, 48, 48, 2.0 ** -5, 2.0 ** -5, 0.0, 0.0)
     parts.append(_pixel_steps(far, 1, rng))
@@ -337,3 +339,16 @@ def test_weakened_filter_is_caught(weak_probe):
     _, _, _, wrong_edge, wrong_common = _step_violations(weak_probe, st)
     print(f"weakened filter: {int(wrong_edge.sum())} wrong per-edge signs, {int(wrong_common.sum())} wrong settled steps")
     assert wrong_edge.any() and wrong_common.any()
+
+
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 63, 1000, 1024 * 45 + 5])
+def test_xcd_block_order_is_a_bijection_with_one_run_per_die(probe, n):
+    """The walks' XCD-aware block order (common.h): a permutation of the
+    launch's blocks in which the blocks dispatched to each die (b mod 8)
+    form one contiguous run of the logical order, in dispatch order."""
+    L = np.array([probe.probe_xcd_block(b, n) for b in range(n)], np.int64)
+    assert np.array_equal(np.sort(L), np.arange(n))
+    for x in range(8):
+        run = L[x::8]
+        if len(run):
+            assert np.array_equal(run, np.arange(run[0], run[0] + len(run)))
