@@ -181,7 +181,8 @@ struct tct_batch {
   std::vector<int> tile_u;
   void* d_desc = nullptr;  // device BatchDesc[n], most expensive blocks first
   int64_t total_items = 0;
-  unsigned long long* d_counter = nullptr;
+  unsigned long long* d_counter = nullptr;  // [kXcds] next free position of each die's work list
+  int64_t* d_lists = nullptr;               // [kXcds][n + 1] positions of the problems' runs in the lists
   int grid_fwd = 0, grid_bwd = 0;  // persistent grid sizes
   int queue_chunk = 1;             // pixel blocks handed out per queue fetch
   std::vector<int32_t*> owned_entries;  // entry caches made for problems given without one

@@ -944,65 +944,119 @@ __global__ __launch_bounds__(64 * kRasterWaves) void entry_raster_kernel(MeshVie
 }
 
 // Batched problems: one persistent launch pulls pixel blocks of every
-// problem from a device work counter.  Problems are listed most expensive
-// block first, so long walks start early and short ones fill the tail.
+// problem from device work lists.  Problems are listed most expensive block
+// first, so long walks start early and short ones fill the tail.  As in the
+// single-problem launches (xcd_block), each problem's blocks are split into
+// kXcds contiguous runs, one per die: list x holds run x of every problem in
+// problem order, and a workgroup takes from the list of its own die (block
+// b runs on die b mod kXcds) until that list is empty, then from the others.
 struct BatchDesc {
   MeshView M;
   GeomView G;
   TileMap tm;
-  int64_t item_begin;  // first queue item of this problem
+  int64_t items;  // pixel blocks of this problem
   const int32_t* entry;
   int user;  // index of the problem in the caller's lists
   int lds_table;
 };
 
+// Run x of a problem of n blocks: first block and length (as xcd_block).
+__host__ __device__ __forceinline__ int64_t xcd_run_begin(int64_t n, int x) {
+  const int64_t per = n / kXcds, rem = n % kXcds;
+  return x * per + (x < rem ? x : rem);
+}
+__host__ __device__ __forceinline__ int64_t xcd_run_length(int64_t n, int x) {
+  return n / kXcds + (x < n % kXcds ? 1 : 0);
+}
+
 template <int MODE>
-__global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __restrict__ D, int nprob, int64_t total,
-                                                         unsigned long long* counter, int chunk,
+__global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __restrict__ D, int nprob,
+                                                         const int64_t* __restrict__ lists,
+                                                         unsigned long long* counters, int chunk,
                                                          const float* const* __restrict__ ins,
                                                          float* const* __restrict__ outs) {
-  __shared__ long long s_item;
+  // lists[x (nprob + 1) + p]: position of problem p's run in list x (its
+  // last entry is the list's length); counters[x]: next free position.
+  // Thread 0 fetches `chunk` positions at a time and resolves each to a
+  // (problem, pixel block) for the whole block; its state lives in LDS so
+  // that nothing of the queue stays live in registers during the walk.
+  __shared__ long long s_k, s_end, s_block;
+  __shared__ int s_list, s_prob;
+  const int home = (int)(blockIdx.x % kXcds);
+  if (threadIdx.x == 0) {
+    s_k = 0;
+    s_end = 0;
+    s_list = home;
+  }
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, (unsigned long long)chunk);
+    if (threadIdx.x == 0) {
+      long long k = s_k, end = s_end;
+      int x = s_list;
+      if (k >= end) {
+        k = -1;
+        for (int g = 0; g < kXcds; ++g) {
+          const int y = (home + g) % kXcds;
+          const long long len = lists[y * (nprob + 1) + nprob];
+          const long long c = (long long)atomicAdd(counters + y, (unsigned long long)chunk);
+          if (c < len) {
+            k = c;
+            end = c + chunk < len ? c + chunk : len;
+            x = y;
+            break;
+          }
+        }
+      }
+      if (k < 0) {
+        s_prob = -1;
+      } else {
+        // The problem whose run holds position k: the last p with
+        // pos[p] <= k (runs may be empty, so several p share a position).
+        const int64_t* pos = lists + x * (nprob + 1);
+        int lo = 0, hi = nprob - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pos[mid] <= k)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        s_prob = lo;
+        s_block = xcd_run_begin(D[lo].items, x) + (k - pos[lo]);
+        s_k = k + 1;
+        s_end = end;
+        s_list = x;
+      }
+    }
     __syncthreads();
-    // The item is the same for the whole block; saying so lets the
-    // descriptor below be read with scalar loads into scalar registers, as
-    // kernel arguments are in the single-problem kernel.
-    const long long raw = s_item;
-    const long long first = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(raw >> 32))
+    // The same for the whole block; saying so lets the descriptor below be
+    // read with scalar loads into scalar registers, as kernel arguments are
+    // in the single-problem kernel.
+    const int p = __builtin_amdgcn_readfirstlane(s_prob);
+    if (p < 0) break;
+    const long long raw = s_block;
+    const long long block = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(raw >> 32))
                                          << 32) |
                                         (unsigned)__builtin_amdgcn_readfirstlane((int)raw));
-    if (first >= total) break;
-    // `chunk` consecutive pixel blocks per fetch (they may span problems).
-    for (long long item = first; item < first + chunk && item < total; ++item) {
-      int lo = 0, hi = nprob - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (D[mid].item_begin <= item)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      lo = __builtin_amdgcn_readfirstlane(lo);
-      const BatchDesc d = D[lo];
-      BlockIO io{};
-      io.entry = d.entry;
-      io.in = ins[d.user];
-      io.out_f32 = outs[d.user];
-      io.lds_table = d.lds_table;
-      if constexpr (MODE == kModeBackAtomic) {
-        __shared__ int tkeys[kBlockWaves * TableShape<MODE>::slots];
-        __shared__ long long tvals[kBlockWaves * TableShape<MODE>::slots];
-        walk_block<MODE, true, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, tkeys, tvals);
-      } else {
-        walk_block<MODE, true, true>(d.M, d.G, d.tm, item - d.item_begin, 0, d.G.na, io, nullptr, nullptr);
-      }
+    const BatchDesc d = D[p];
+    BlockIO io{};
+    io.entry = d.entry;
+    io.in = ins[d.user];
+    io.out_f32 = outs[d.user];
+    io.lds_table = d.lds_table;
+    if constexpr (MODE == kModeBackAtomic) {
+      __shared__ int tkeys[kBlockWaves * TableShape<MODE>::slots];
+      __shared__ long long tvals[kBlockWaves * TableShape<MODE>::slots];
+      walk_block<MODE, true, true>(d.M, d.G, d.tm, block, 0, d.G.na, io, tkeys, tvals);
+    } else {
+      walk_block<MODE, true, true>(d.M, d.G, d.tm, block, 0, d.G.na, io, nullptr, nullptr);
     }
   }
 }
 
-__global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
+__global__ void reset_counters_kernel(unsigned long long* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0ull;
+}
 
 // Listed rays (trace): either pixel ray ids, or explicit S/P/U/V arrays.
 template <int MODE>
@@ -1373,10 +1427,20 @@ tct_status batch_build(const tct_mesh* const* meshes, const tct_geom* const* geo
   int64_t item = 0;
   for (int k = 0; k < n; ++k) {
     sorted[k] = desc[order[k]];
-    sorted[k].item_begin = item;
-    item += (int64_t)sorted[k].tm.nbu * sorted[k].tm.nbv * sorted[k].G.na;
+    sorted[k].items = (int64_t)sorted[k].tm.nbu * sorted[k].tm.nbv * sorted[k].G.na;
+    item += sorted[k].items;
   }
   b->total_items = item;
+  // Per-die work lists: run x of every problem, in problem order.
+  std::vector<int64_t> lists((size_t)kXcds * (n + 1));
+  for (int x = 0; x < kXcds; ++x) {
+    int64_t at = 0;
+    for (int k = 0; k < n; ++k) {
+      lists[(size_t)x * (n + 1) + k] = at;
+      at += xcd_run_length(sorted[k].items, x);
+    }
+    lists[(size_t)x * (n + 1) + n] = at;
+  }
   auto fail = [&](hipError_t e, const char* what) {
     batch_free(b);
     return hip_fail(e, what);
@@ -1403,8 +1467,13 @@ tct_status batch_build(const tct_mesh* const* meshes, const tct_geom* const* geo
   if ((e = hipMalloc(&b->d_desc, sizeof(BatchDesc) * (size_t)n)) != hipSuccess) return fail(e, "hipMalloc(batch)");
   if ((e = hipMemcpy(b->d_desc, sorted.data(), sizeof(BatchDesc) * (size_t)n, hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e, "hipMemcpy(batch)");
-  if ((e = hipMalloc((void**)&b->d_counter, sizeof(unsigned long long))) != hipSuccess)
-    return fail(e, "hipMalloc(batch counter)");
+  if ((e = hipMalloc((void**)&b->d_lists, sizeof(int64_t) * lists.size())) != hipSuccess)
+    return fail(e, "hipMalloc(batch lists)");
+  if ((e = hipMemcpy(b->d_lists, lists.data(), sizeof(int64_t) * lists.size(), hipMemcpyHostToDevice)) !=
+      hipSuccess)
+    return fail(e, "hipMemcpy(batch lists)");
+  if ((e = hipMalloc((void**)&b->d_counter, sizeof(unsigned long long) * kXcds)) != hipSuccess)
+    return fail(e, "hipMalloc(batch counters)");
   int cus = 0, occ_f = 0, occ_b = 0;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device)) != hipSuccess)
     return fail(e, "hipDeviceGetAttribute");
@@ -1424,19 +1493,22 @@ void batch_free(tct_batch* b) {
   if (!b) return;
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_counter) (void)hipFree(b->d_counter);
+  if (b->d_lists) (void)hipFree(b->d_lists);
   for (int32_t* p : b->owned_entries) (void)hipFree(p);
   delete b;
 }
 
 tct_status batch_walk(tct_batch* b, int mode, const tct_vecset* in, const tct_vecset* out, hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, b->d_counter);
+  // A kernel, not a memset, clears the counters: the launch may be captured
+  // into a graph and replayed.
+  hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, b->d_counter, kXcds);
   const BatchDesc* D = (const BatchDesc*)b->d_desc;
   if (mode == kModeForward) {
-    hipLaunchKernelGGL(batch_walk_kernel<kModeForward>, dim3(b->grid_fwd), dim3(256), 0, s, D, b->n, b->total_items,
+    hipLaunchKernelGGL(batch_walk_kernel<kModeForward>, dim3(b->grid_fwd), dim3(256), 0, s, D, b->n, b->d_lists,
                        b->d_counter, b->queue_chunk, (const float* const*)in->d_ptrs, out->d_ptrs);
   } else if (mode == kModeBackAtomic) {
     hipLaunchKernelGGL(batch_walk_kernel<kModeBackAtomic>, dim3(b->grid_bwd), dim3(256), 0, s, D, b->n,
-                       b->total_items, b->d_counter, b->queue_chunk, (const float* const*)in->d_ptrs, out->d_ptrs);
+                       b->d_lists, b->d_counter, b->queue_chunk, (const float* const*)in->d_ptrs, out->d_ptrs);
   } else {
     set_error("batch_walk: unsupported mode");
     return TCT_E_ARG;
