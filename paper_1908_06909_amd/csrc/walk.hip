@@ -300,12 +300,13 @@ __device__ int find_entry(const MeshView& M, const Ray& r, St& st) {
 //
 // The tables sum in 64-bit fixed point: LDS integer atomics run several
 // times faster than float ones on this chip.  Each term t = L y_j |d| is
-// rounded to a multiple of 2^-54 M, M >= 2^(e-1) the wavefront's largest
-// |y_j| |d| (2^e the next power of two), and at most 64 terms (one per ray of
-// the wavefront) meet in a slot per window, so the integer sum stays below
-// 2^60 and is exact; the flush converts it back (or records it as it is).
-// Every term keeps an absolute error below 2^-54 2^e, far below a float32
-// rounding of the terms that matter.
+// rounded to a multiple of 2^-50 2^e, 2^e the next power of two above the
+// wavefront's largest |y_j| |d|, and at most 64 terms (one per ray of the
+// wavefront) meet in a slot per window, so the integer sum stays below 2^56
+// and is exact; the flush converts it back (or records it as it is).  Every
+// term keeps an absolute error below 2^-51 2^e, far below a float32 rounding
+// of the terms that matter.  Terms below 2^51 in magnitude are converted to
+// integers with one float64 addition (round_to_i64).
 constexpr int kScatterSlots = 384;
 constexpr int kScatterWindow = 24;
 constexpr int kListSlots = 768;
@@ -327,16 +328,35 @@ __device__ __forceinline__ int lds_cas(lds_i32* p, int tet) {
   return expected;
 }
 
+// Multiplicative (Fibonacci) hash in 24 bits, since 24-bit multiplies run
+// at full rate and 32-bit ones at a quarter: the low 24 bits of k A, A the
+// golden-ratio fraction of 2^24, are the fractional part of k times 0.618,
+// which spreads consecutive keys over the table; its top 20 bits are scaled
+// to the table size.
 template <int kSlots>
 __device__ __forceinline__ unsigned table_home(int tet) {
-  return __umulhi((unsigned)tet * 2654435761u, (unsigned)kSlots);
+  static_assert(kSlots < (1 << 12), "slot index times 2^20 must fit 32 bits");
+  const unsigned h = __umul24((unsigned)tet & 0xFFFFFFu, 0x9E3779u);
+  return (((h >> 4) & 0xFFFFFu) * (unsigned)kSlots) >> 20;
 }
 
-// Adds v (scaled to fixed point) to the slot of `tet`; false when the
+// x rounded to the nearest integer (ties to even), |x| < 2^51: in float64,
+// x + 1.5 2^52 falls in [2^52, 2^53), where consecutive values are 1 apart,
+// so the addition rounds x to an integer and the sum's bit pattern exceeds
+// that of 1.5 2^52 (0x4338000000000000, low word zero) by exactly that
+// integer.
+__device__ __forceinline__ long long round_to_i64(float x) {
+  const double y = (double)x + 0x1.8p52;
+  const int hi = __double2hiint(y) - 0x43380000;
+  const unsigned lo = (unsigned)__double2loint(y);
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | lo);
+}
+
+// Adds the fixed-point term m to the slot of `tet`; false when the
 // tetrahedron finds no slot within kLdsProbes probes (the caller then adds
 // the term elsewhere).
 template <int kSlots>
-__device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int tet, float v, float scale) {
+__device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int tet, long long m) {
   unsigned slot = table_home<kSlots>(tet);
   // Most segments find their tetrahedron already placed by a neighbouring
   // ray of the bundle: a plain read settles those without an atomic.
@@ -351,7 +371,7 @@ __device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int
     }
     if (k != -1 && k != tet) return false;
   }
-  __hip_atomic_fetch_add(vals + slot, __float2ll_rn(v * scale), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  __hip_atomic_fetch_add(vals + slot, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   return true;
 }
 
@@ -369,7 +389,8 @@ struct WalkOut {
   // FWD
   const float* x = nullptr;
   double acc = 0.0;
-  // BWD / GATHER_FILL: weight = y_j * |d|
+  // BWD / GATHER_FILL: weight = y_j * |d|; the table walks hold it times
+  // lds_scale, so that a segment's fixed-point term is one product away
   float weight = 0.f;
   float* xhat = nullptr;
   lds_i32* lds_keys = nullptr;  // the wavefront's accumulation table (BWD)
@@ -473,6 +494,13 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     return false;
   }
   w.steps++;
+  // Next tetrahedron across the exit face (local face index loc[k]): the
+  // record's load is issued as soon as the face is known, so that its
+  // latency overlaps the crossing and the segment's accumulation.
+  const int tet = w.tet;
+  const unsigned sh = 4u * (unsigned)k;
+  unsigned f = (w.loc >> sh) & 3u;
+  float4 rec = M.faces[(size_t)(((unsigned)tet << 2) | f)];
   const bool k0 = k == 0, k2 = k == 2;
   const float3 ei = make_float3(k2 ? e0.x : (k0 ? e1.x : e2.x), k2 ? e0.y : (k0 ? e1.y : e2.y),
                                 k2 ? e0.z : (k0 ? e1.z : e2.z));
@@ -496,24 +524,20 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   else
     dt = __builtin_amdgcn_fmed3f(dt, 0.0f, (float)fmax(0.5 - w.s_in, 0.0));
   if (dt == 0.f) st.add_zero();
-  // Next tetrahedron across the exit face (local face index loc[k]).
-  const int tet = w.tet;
-  const unsigned sh = 4u * (unsigned)k;
-  unsigned f = (w.loc >> sh) & 3u;
-  float4 rec = M.faces[(size_t)(((unsigned)tet << 2) | f)];
   if constexpr (MODE == kModeForward) {
     o.acc = fma((double)dt, (double)w.xcur, o.acc);  // the product is exact
   } else if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
     if (dt > 0.f) {
-      const float v = dt * o.weight;
-      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, v, o.lds_scale)) {
+      const float v = dt * o.weight;  // in units of 2^-scale_exp
+      const long long m = round_to_i64(v);
+      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m)) {
         if constexpr (MODE == kModeBackFixed) {
-          atomicAdd(o.acc64 + tet, (unsigned long long)__float2ll_rn(v * o.lds_scale));
+          atomicAdd(o.acc64 + tet, (unsigned long long)m);
         } else if constexpr (MODE == kModeGatherFill) {
           const int64_t p = (int64_t)atomicAdd(o.gather.cursor, 1ull);
-          gather_record(o.gather, p, tet, o.scale_exp, __float2ll_rn(v * o.lds_scale));
+          gather_record(o.gather, p, tet, o.scale_exp, m);
         } else {
-          unsafeAtomicAdd(o.xhat + tet, v);
+          unsafeAtomicAdd(o.xhat + tet, ldexpf(v, -o.scale_exp));
         }
       }
     }
@@ -693,7 +717,8 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     if constexpr (MODE == kModeBackFixed) {
       // One scale for the whole launch, so that every sum is an exact
       // integer whatever the order of the additions.
-      o.lds_scale = ldexpf(1.0f, *io.scale_exp);
+      o.scale_exp = *io.scale_exp;
+      o.lds_scale = ldexpf(1.0f, o.scale_exp);
       o.acc64 = io.acc64;
     } else {
       if constexpr (MODE == kModeGatherFill) o.gather = io.gather;
@@ -710,9 +735,10 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       __builtin_amdgcn_wave_barrier();
       int ex = 0;
       (void)frexpf(__uint_as_float(*wm), &ex);
-      o.scale_exp = min(54 - ex, 120);
+      o.scale_exp = min(50 - ex, 120);
       o.lds_scale = ldexpf(1.0f, o.scale_exp);
     }
+    o.weight *= o.lds_scale;  // a power of two: exact
     // The wavefront's rays advance together in windows of kWindow
     // steps; after each window its table is added to xhat and cleared, so it
     // only ever holds the tetrahedra of one window of the ray bundle.
@@ -750,7 +776,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
             if constexpr (MODE == kModeBackFixed)
               atomicAdd(io.acc64 + key, (unsigned long long)vals[k]);
             else
-              unsafeAtomicAdd(io.out_f32 + key, (float)ldexp((double)vals[k], -ilogbf(o.lds_scale)));
+              unsafeAtomicAdd(io.out_f32 + key, (float)ldexp((double)vals[k], -o.scale_exp));
             keys[k] = -1;
             vals[k] = 0;
           }
@@ -1261,7 +1287,8 @@ tct_status backproject_atomic(const tct_mesh* m, const tct_geom* g, const float*
 // Reproducible scatter (TCT_BP_FIXED).  Every term L y_j |d_j| is rounded
 // to a multiple of 2^-scale_exp, one scale for the launch: 2^e bounds the
 // largest |y_j| |d_j| (|d_j| <= the longest pixel ray of the angle range)
-// and K = 62 - ceil(log2(rays)), so each term is below 2^K in magnitude and
+// and K = min(50, 62 - ceil(log2(rays))), so each term is below 2^K in
+// magnitude (within the range of the walk's float-to-integer rounding) and
 // no tetrahedron's sum of at most `rays` terms can reach 2^62.  The block
 // tables and the global sums then add integers, exactly, in any order.
 // Scratch layout of the reproducible scatter: [max |y| bits, scale exponent,
@@ -1292,7 +1319,7 @@ static tct_status backproject_fixed_in(const tct_mesh* m, const tct_geom* g, con
   }
   int bits = 1;
   while (bits < 62 && ((int64_t)1 << bits) < nrays) ++bits;
-  const int K = 62 - bits;
+  const int K = std::min(50, 62 - bits);
   unsigned long long* acc = nullptr;
   unsigned* max_bits = (unsigned*)scratch;
   int* scale_exp = (int*)(scratch + 4);
