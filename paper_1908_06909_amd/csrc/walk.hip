@@ -355,12 +355,15 @@ __device__ __forceinline__ long long round_to_i64(float x) {
 // Adds the fixed-point term m to the slot of `tet`; false when the
 // tetrahedron finds no slot within kLdsProbes probes (the caller then adds
 // the term elsewhere).
+// `slot` is the key's home slot and `seen` what a plain read of it returned
+// earlier in the window (a slot, once claimed, keeps its key until the
+// window's flush, so an earlier read that found the key is still right).
 template <int kSlots>
-__device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int tet, long long m) {
-  unsigned slot = table_home<kSlots>(tet);
+__device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int tet, long long m, unsigned slot,
+                                               int seen) {
   // Most segments find their tetrahedron already placed by a neighbouring
-  // ray of the bundle: a plain read settles those without an atomic.
-  int k = keys[slot];
+  // ray of the bundle: the plain read settles those without an atomic.
+  int k = seen;
   if (k != tet) k = lds_cas(keys + slot, tet);
   if (k != -1 && k != tet) {
 #pragma unroll 1
@@ -501,6 +504,14 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   const unsigned sh = 4u * (unsigned)k;
   unsigned f = (w.loc >> sh) & 3u;
   float4 rec = M.faces[(size_t)(((unsigned)tet << 2) | f)];
+  // Table walks: the plain read of the tetrahedron's home slot goes out
+  // with it, its latency overlapping the crossing too.
+  unsigned home = 0;
+  int seen = -1;
+  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
+    home = table_home<TableShape<MODE>::slots>(tet);
+    seen = o.lds_keys[home];
+  }
   const bool k0 = k == 0, k2 = k == 2;
   const float3 ei = make_float3(k2 ? e0.x : (k0 ? e1.x : e2.x), k2 ? e0.y : (k0 ? e1.y : e2.y),
                                 k2 ? e0.z : (k0 ? e1.z : e2.z));
@@ -530,7 +541,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     if (dt > 0.f) {
       const float v = dt * o.weight;  // in units of 2^-scale_exp
       const long long m = round_to_i64(v);
-      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m)) {
+      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m, home, seen)) {
         if constexpr (MODE == kModeBackFixed) {
           atomicAdd(o.acc64 + tet, (unsigned long long)m);
         } else if constexpr (MODE == kModeGatherFill) {
