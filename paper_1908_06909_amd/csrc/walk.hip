@@ -561,6 +561,24 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     o.out_len[o.cursor] = dt * r.dn;
     o.cursor++;
   }
+  // What does not need the record is done while it is in flight: the entry
+  // slots (slot k takes v), the ray parameter, and the first half of the
+  // local-index remap.  All four index fields at once: adding 7 - f to a
+  // field sets its bit 3 exactly when p > f, and adding 8 - back to the rank
+  // sets it exactly when r >= back; the fields hold at most 10, so no carry
+  // crosses into the next.  (The field of slot k, whose vertex is not on the
+  // face, is replaced.)
+  const unsigned L = w.loc;
+  const unsigned R = L - (((L + 0x7777u - f * 0x1111u) >> 3) & 0x1111u);
+  w.a0 = make_float3(k == 0 ? v.x : w.a0.x, k == 0 ? v.y : w.a0.y, k == 0 ? v.z : w.a0.z);
+  w.a1 = make_float3(k == 1 ? v.x : w.a1.x, k == 1 ? v.y : w.a1.y, k == 1 ? v.z : w.a1.z);
+  w.a2 = make_float3(k == 2 ? v.x : w.a2.x, k == 2 ? v.y : w.a2.y, k == 2 ? v.z : w.a2.z);
+  w.s_in += (double)dt;  // float64: no rounding drift along the ray
+  unsigned Rk = R;
+  // (An empty statement that takes these values, so the compiler computes
+  // them here rather than sinking them behind the wait for the record.)
+  asm volatile("" : "+v"(w.a0.x), "+v"(w.a0.y), "+v"(w.a0.z), "+v"(w.a1.x), "+v"(w.a1.y), "+v"(w.a1.z),
+               "+v"(w.a2.x), "+v"(w.a2.y), "+v"(w.a2.z), "+v"(w.s_in), "+v"(Rk));
   // Keep the record one 16-byte load consumed here; otherwise the compiler
   // splits it into four loads sunk into the next step, which serialises the
   // dependent fetch behind the next step's arithmetic.
@@ -571,22 +589,12 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     return false;
   }
   unsigned back = (unsigned)packed & 3u;
-  // All four fields at once.  Adding 7 - f to a field sets its bit 3
-  // exactly when p > f, and adding 8 - back to the rank sets it exactly when
-  // r >= back; the fields hold at most 10, so no carry crosses into the next.
-  // (The field of slot k, whose vertex is not on the face, is replaced.)
-  const unsigned L = w.loc;
-  const unsigned R = L - (((L + 0x7777u - f * 0x1111u) >> 3) & 0x1111u);
-  const unsigned N = R + (((R + 0x8888u - back * 0x1111u) >> 3) & 0x1111u);
-  w.a0 = make_float3(k == 0 ? v.x : w.a0.x, k == 0 ? v.y : w.a0.y, k == 0 ? v.z : w.a0.z);
-  w.a1 = make_float3(k == 1 ? v.x : w.a1.x, k == 1 ? v.y : w.a1.y, k == 1 ? v.z : w.a1.z);
-  w.a2 = make_float3(k == 2 ? v.x : w.a2.x, k == 2 ? v.y : w.a2.y, k == 2 ? v.z : w.a2.z);
+  const unsigned N = Rk + (((Rk + 0x8888u - back * 0x1111u) >> 3) & 0x1111u);
   // Slot k takes v's new index; the neighbour's opposite vertex is `back`.
   const unsigned fieldk = 0xFu << sh;
   w.loc = (((N & 0xFFFu) & ~fieldk) | ((N >> 12) << sh)) | (back << 12);
   w.v = xyz(rec);
   w.tet = packed >> 2;
-  w.s_in += (double)dt;  // float64: no rounding drift along the ray
   if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
   return true;
 }
