@@ -354,17 +354,14 @@ __device__ __forceinline__ long long round_to_i64(float x) {
 
 // Adds the fixed-point term m to the slot of `tet`; false when the
 // tetrahedron finds no slot within kLdsProbes probes (the caller then adds
-// the term elsewhere).
-// `slot` is the key's home slot and `seen` what a plain read of it returned
-// earlier in the window (a slot, once claimed, keeps its key until the
-// window's flush, so an earlier read that found the key is still right).
+// the term elsewhere).  `slot` is the key's home slot and `claimed` what the
+// compare-and-swap that claimed it for `tet` returned, issued when the ray
+// entered the tetrahedron (a slot keeps its key until the window's flush):
+// -1 or `tet` mean the home slot is the tetrahedron's.
 template <int kSlots>
 __device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int tet, long long m, unsigned slot,
-                                               int seen) {
-  // Most segments find their tetrahedron already placed by a neighbouring
-  // ray of the bundle: the plain read settles those without an atomic.
-  int k = seen;
-  if (k != tet) k = lds_cas(keys + slot, tet);
+                                               int claimed) {
+  int k = claimed;
   if (k != -1 && k != tet) {
 #pragma unroll 1
     for (int p = 1; p < kLdsProbes; ++p) {
@@ -429,6 +426,7 @@ struct WalkState {
   unsigned loc;
   double s_in;  // ray parameter where the ray entered the current tetrahedron
   float xcur;  // forward projection: x of the current tetrahedron
+  int claim;   // table walks: old key returned by the claim of the tetrahedron's home slot
   int steps;
   // Every ray of the wavefront ends beyond the mesh (ends_beyond_mesh), so
   // segments need no clamp at the end point; the same for the whole
@@ -504,14 +502,6 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   const unsigned sh = 4u * (unsigned)k;
   unsigned f = (w.loc >> sh) & 3u;
   float4 rec = M.faces[(size_t)(((unsigned)tet << 2) | f)];
-  // Table walks: the plain read of the tetrahedron's home slot goes out
-  // with it, its latency overlapping the crossing too.
-  unsigned home = 0;
-  int seen = -1;
-  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
-    home = table_home<TableShape<MODE>::slots>(tet);
-    seen = o.lds_keys[home];
-  }
   const bool k0 = k == 0, k2 = k == 2;
   const float3 ei = make_float3(k2 ? e0.x : (k0 ? e1.x : e2.x), k2 ? e0.y : (k0 ? e1.y : e2.y),
                                 k2 ? e0.z : (k0 ? e1.z : e2.z));
@@ -541,7 +531,8 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     if (dt > 0.f) {
       const float v = dt * o.weight;  // in units of 2^-scale_exp
       const long long m = round_to_i64(v);
-      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m, home, seen)) {
+      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m,
+                                                   table_home<TableShape<MODE>::slots>(tet), w.claim)) {
         if constexpr (MODE == kModeBackFixed) {
           atomicAdd(o.acc64 + tet, (unsigned long long)m);
         } else if constexpr (MODE == kModeGatherFill) {
@@ -595,6 +586,10 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   w.loc = (((N & 0xFFFu) & ~fieldk) | ((N >> 12) << sh)) | (back << 12);
   w.v = xyz(rec);
   w.tet = packed >> 2;
+  // Table walks claim the new tetrahedron's home slot now; the old key comes
+  // back while the next step computes, and is needed only at its end.
+  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill)
+    w.claim = lds_cas(o.lds_keys + table_home<TableShape<MODE>::slots>(w.tet), w.tet);
   if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
   return true;
 }
@@ -762,6 +757,9 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     // steps; after each window its table is added to xhat and cleared, so it
     // only ever holds the tetrahedra of one window of the ray bundle.
     for (;;) {
+      // Each step claims the slot of the tetrahedron it enters (walk_step);
+      // the flush has cleared the table, so the current ones claim again.
+      if (alive) w.claim = lds_cas(keys + table_home<kSlots>(w.tet), w.tet);
 #pragma unroll 1
       for (int k = 0; k < kWindow && alive; ++k) alive = walk_step<MODE>(M, r, q, w, o, st);
       // LDS operations of one wavefront complete in order: the flush sees
@@ -770,19 +768,23 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       __builtin_amdgcn_wave_barrier();
       if constexpr (MODE == kModeGatherFill) {
         // One record per occupied slot, at consecutive positions reserved
-        // with one atomic for the wavefront.
+        // with one atomic for the wavefront.  (Slots claimed ahead by a
+        // window's last step hold zero and are only cleared.)
         unsigned total = 0;
-        for (int k = lane; k < kSlots; k += 64) total += __popcll(__ballot(keys[k] >= 0));
+        for (int k = lane; k < kSlots; k += 64) total += __popcll(__ballot(keys[k] >= 0 && vals[k] != 0));
         unsigned long long base = 0;
         if (lane == 0 && total) base = atomicAdd(o.gather.cursor, (unsigned long long)total);
         base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
                (unsigned)__builtin_amdgcn_readfirstlane((int)base);
         for (int k = lane; k < kSlots; k += 64) {
           const int key = keys[k];
-          const unsigned long long m = __ballot(key >= 0);
+          const long long v = vals[k];
+          const unsigned long long m = __ballot(key >= 0 && v != 0);
           if (key >= 0) {
-            const int64_t p = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
-            gather_record(o.gather, p, key, o.scale_exp, vals[k]);
+            if (v != 0) {
+              const int64_t p = (int64_t)base + __popcll(m & ((1ull << lane) - 1ull));
+              gather_record(o.gather, p, key, o.scale_exp, v);
+            }
             keys[k] = -1;
             vals[k] = 0;
           }
@@ -792,10 +794,13 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
         for (int k = lane; k < kSlots; k += 64) {
           const int key = keys[k];
           if (key >= 0) {
-            if constexpr (MODE == kModeBackFixed)
-              atomicAdd(io.acc64 + key, (unsigned long long)vals[k]);
-            else
-              unsafeAtomicAdd(io.out_f32 + key, (float)ldexp((double)vals[k], -o.scale_exp));
+            const long long v = vals[k];
+            if (v != 0) {
+              if constexpr (MODE == kModeBackFixed)
+                atomicAdd(io.acc64 + key, (unsigned long long)v);
+              else
+                unsafeAtomicAdd(io.out_f32 + key, (float)ldexp((double)v, -o.scale_exp));
+            }
             keys[k] = -1;
             vals[k] = 0;
           }
