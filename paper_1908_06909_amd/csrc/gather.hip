@@ -42,15 +42,15 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
 __global__ void zero_u64_one_kernel(unsigned long long* p) { *p = 0ull; }
 
 // Records into their tetrahedron's list: list t is [off[t], off[t] + counts
-// of t); cur[t] (zeroed) hands out its positions.
-__global__ void scatter_records_kernel(const int32_t* tet, const int32_t* scale, const int64_t* m, int64_t n,
-                                       const int64_t* off, int32_t* cur, int32_t* sscale, int64_t* sm) {
+// of t); cur[t] (zeroed) hands out its positions.  One 16-byte load and one
+// 16-byte store per record.
+__global__ void scatter_records_kernel(const GatherRecord* rec, int64_t n, const int64_t* off, int32_t* cur,
+                                       GatherRecord* list) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  const int t = tet[r];
-  const int64_t p = off[t] + atomicAdd(cur + t, 1);
-  sscale[p] = scale[r];
-  sm[p] = m[r];
+  const GatherRecord x = rec[r];
+  const int64_t p = off[x.tet] + atomicAdd(cur + x.tet, 1);
+  list[p] = x;
 }
 
 // 128-bit two's complement integers for exact sums.
@@ -85,8 +85,8 @@ __device__ __forceinline__ I128 i128_scaled(long long m, int k) {
 constexpr int kSumWaves = 4;
 constexpr int kMaxScaleSpread = 36;
 
-__global__ __launch_bounds__(64 * kSumWaves) void exact_sum_kernel(const int64_t* off, const int32_t* sscale,
-                                                                   const int64_t* sm, double* acc, int nt) {
+__global__ __launch_bounds__(64 * kSumWaves) void exact_sum_kernel(const int64_t* off, const GatherRecord* list,
+                                                                   double* acc, int nt) {
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * kSumWaves + (threadIdx.x >> 6);
   if (t >= nt) return;
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64 * kSumWaves) void exact_sum_kernel(const int64_t
   if (b == e) return;
   int smin = 1 << 30, smax = -(1 << 30);
   for (int64_t i = b + lane; i < e; i += 64) {
-    const int sc = sscale[i];
+    const int sc = list[i].scale;
     smin = min(smin, sc);
     smax = max(smax, sc);
   }
@@ -105,7 +105,10 @@ __global__ __launch_bounds__(64 * kSumWaves) void exact_sum_kernel(const int64_t
   }
   const int sref = min(smax, smin + kMaxScaleSpread);
   I128 s{0ull, 0ll};
-  for (int64_t i = b + lane; i < e; i += 64) s = i128_add(s, i128_scaled(sm[i], sref - sscale[i]));
+  for (int64_t i = b + lane; i < e; i += 64) {
+    const GatherRecord x = list[i];
+    s = i128_add(s, i128_scaled(x.m, sref - x.scale));
+  }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     I128 x;
@@ -231,8 +234,9 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
   // from the records per angle seen so far.
   const int64_t kBudget = (int64_t)1 << 28;
   AsyncBuf<double> acc(s);
-  AsyncBuf<int32_t> counts(s), rtet(s), rscale(s), sscale(s);
-  AsyncBuf<int64_t> scan_sums(s), offsets(s), rm(s), sm(s);
+  AsyncBuf<int32_t> counts(s);
+  AsyncBuf<GatherRecord> rec(s), list(s);
+  AsyncBuf<int64_t> scan_sums(s), offsets(s);
   AsyncBuf<unsigned long long> cursor(s);
   TCT_HIP(acc.ensure(nt));
   TCT_HIP(counts.ensure(nt));
@@ -249,13 +253,11 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
     int64_t cap = std::max<int64_t>(1024, (int64_t)(rec_per_angle * na_c * 1.25));
     int64_t total = 0;
     for (;;) {
-      TCT_HIP(rtet.ensure(cap));
-      TCT_HIP(rscale.ensure(cap));
-      TCT_HIP(rm.ensure(cap));
+      TCT_HIP(rec.ensure(cap));
       hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, counts.p, (int64_t)nt);
       hipLaunchKernelGGL(zero_u64_one_kernel, dim3(1), dim3(1), 0, s, cursor.p);
       TCT_HIP(hipGetLastError());
-      const GatherOut go{rtet.p, rscale.p, rm.p, counts.p, cursor.p, cap};
+      const GatherOut go{rec.p, counts.p, cursor.p, cap};
       tct_status st = launch_pixel_walk(kModeGatherFill, m, g, a0, na_c, entry, proj, nullptr, nullptr, &go, tile_u,
                                         s);
       if (st != TCT_OK) return st;
@@ -268,15 +270,14 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
     }
     rec_per_angle = std::max(1.0, (double)total / na_c);
     if (total > 0) {
-      TCT_HIP(sscale.ensure(total));
-      TCT_HIP(sm.ensure(total));
+      TCT_HIP(list.ensure(total));
       tct_status st = exclusive_scan_counts(counts.p, offsets.p, nt, scan_sums.p, s);
       if (st != TCT_OK) return st;
       hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, counts.p, (int64_t)nt);
-      hipLaunchKernelGGL(scatter_records_kernel, dim3(grid_of(total, 256)), dim3(256), 0, s, rtet.p, rscale.p, rm.p,
-                         total, offsets.p, counts.p, sscale.p, sm.p);
+      hipLaunchKernelGGL(scatter_records_kernel, dim3(grid_of(total, 256)), dim3(256), 0, s, rec.p, total,
+                         offsets.p, counts.p, list.p);
       hipLaunchKernelGGL(exact_sum_kernel, dim3(grid_of(nt, kSumWaves)), dim3(64 * kSumWaves), 0, s, offsets.p,
-                         sscale.p, sm.p, acc.p, nt);
+                         list.p, acc.p, nt);
       TCT_HIP(hipGetLastError());
     }
     a0 += na_c;

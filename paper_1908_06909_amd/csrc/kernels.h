@@ -20,13 +20,17 @@ enum WalkMode {
 // Explicit per-tetrahedron lists (TCT_BP_GATHER): records of one chunk of
 // angles, each the exact fixed-point sum m 2^-scale over the rays of one
 // wavefront and one window of steps that cross tetrahedron `tet` with
-// positive length (scale: the wavefront's, a power of two).  counts[tet]
-// counts the tetrahedron's records; cursor counts all records, also those
-// beyond cap, which are not written.
+// positive length (scale: the wavefront's, a power of two).  One 16-byte
+// record, written and moved with single 16-byte accesses.
+struct alignas(16) GatherRecord {
+  long long m;
+  int32_t tet;
+  int32_t scale;
+};
+// The fill walk's output: counts[tet] counts the tetrahedron's records;
+// cursor counts all records, also those beyond cap, which are not written.
 struct GatherOut {
-  int32_t* tet;
-  int32_t* scale;
-  int64_t* m;
+  GatherRecord* rec;
   int32_t* counts;
   unsigned long long* cursor;
   int64_t cap;
