@@ -39,16 +39,19 @@ __global__ void zero_i32_kernel(int32_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
-__global__ void zero_u64_one_kernel(unsigned long long* p) { *p = 0ull; }
+__global__ void zero_u64_small_kernel(unsigned long long* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
 
 // Records into their tetrahedron's list: list t is [off[t], off[t] + counts
 // of t); cur[t] (zeroed) hands out its positions.  One 16-byte load and one
-// 16-byte store per record.
-__global__ void scatter_records_kernel(const GatherRecord* rec, int64_t n, const int64_t* off, int32_t* cur,
-                                       GatherRecord* list) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const GatherRecord x = rec[r];
+// 16-byte store per record.  blockIdx.y is the record region (its first
+// nrec[y] records are written, region size gcap).
+__global__ void scatter_records_kernel(const GatherRecord* rec, const unsigned long long* nrec, int64_t gcap,
+                                       const int64_t* off, int32_t* cur, GatherRecord* list) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nrec[blockIdx.y]) return;
+  const GatherRecord x = rec[(int64_t)blockIdx.y * gcap + i];
   const int64_t p = off[x.tet] + atomicAdd(cur + x.tet, 1);
   list[p] = x;
 }
@@ -242,7 +245,7 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
   TCT_HIP(counts.ensure(nt));
   TCT_HIP(scan_sums.ensure((size_t)nt / kScanItems + 1));
   TCT_HIP(offsets.ensure((size_t)nt + 1));
-  TCT_HIP(cursor.ensure(1));
+  TCT_HIP(cursor.ensure(kGatherGroups));
   hipLaunchKernelGGL(zero_f64_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, acc.p, (int64_t)nt);
   TCT_HIP(hipGetLastError());
   double rec_per_angle = 16.0 * (double)rays_per_angle;
@@ -250,23 +253,30 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
   int a0 = a_begin;
   while (a0 < a_end) {
     int na_c = (int)std::max<double>(1.0, std::min<double>(a_end - a0, std::floor(kBudget / rec_per_angle)));
-    int64_t cap = std::max<int64_t>(1024, (int64_t)(rec_per_angle * na_c * 1.25));
-    int64_t total = 0;
+    // Per region: an even share of the expected records, with room for the
+    // regions' spread.
+    int64_t gcap = std::max<int64_t>(1024, (int64_t)(rec_per_angle * na_c * 1.25) / kGatherGroups);
+    int64_t total = 0, most = 0;
+    unsigned long long need[kGatherGroups];
     for (;;) {
-      TCT_HIP(rec.ensure(cap));
+      TCT_HIP(rec.ensure((size_t)gcap * kGatherGroups));
       hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, counts.p, (int64_t)nt);
-      hipLaunchKernelGGL(zero_u64_one_kernel, dim3(1), dim3(1), 0, s, cursor.p);
+      hipLaunchKernelGGL(zero_u64_small_kernel, dim3(1), dim3(kGatherGroups), 0, s, cursor.p, kGatherGroups);
       TCT_HIP(hipGetLastError());
-      const GatherOut go{rec.p, counts.p, cursor.p, cap};
+      const GatherOut go{rec.p, counts.p, cursor.p, gcap};
       tct_status st = launch_pixel_walk(kModeGatherFill, m, g, a0, na_c, entry, proj, nullptr, nullptr, &go, tile_u,
                                         s);
       if (st != TCT_OK) return st;
-      unsigned long long need = 0;
-      TCT_HIP(hipMemcpyAsync(&need, cursor.p, sizeof(need), hipMemcpyDeviceToHost, s));
+      TCT_HIP(hipMemcpyAsync(need, cursor.p, sizeof(need), hipMemcpyDeviceToHost, s));
       TCT_HIP(hipStreamSynchronize(s));
-      total = (int64_t)need;
-      if (total <= cap) break;
-      cap = total + total / 8;  // every record fits on the second pass
+      total = 0;
+      most = 0;
+      for (int k = 0; k < kGatherGroups; ++k) {
+        total += (int64_t)need[k];
+        most = std::max<int64_t>(most, (int64_t)need[k]);
+      }
+      if (most <= gcap) break;
+      gcap = most + most / 8;  // every record fits on the second pass
     }
     rec_per_angle = std::max(1.0, (double)total / na_c);
     if (total > 0) {
@@ -274,8 +284,8 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
       tct_status st = exclusive_scan_counts(counts.p, offsets.p, nt, scan_sums.p, s);
       if (st != TCT_OK) return st;
       hipLaunchKernelGGL(zero_i32_kernel, dim3(grid_of(nt, 256)), dim3(256), 0, s, counts.p, (int64_t)nt);
-      hipLaunchKernelGGL(scatter_records_kernel, dim3(grid_of(total, 256)), dim3(256), 0, s, rec.p, total,
-                         offsets.p, counts.p, list.p);
+      hipLaunchKernelGGL(scatter_records_kernel, dim3(grid_of(most, 256), kGatherGroups), dim3(256), 0, s, rec.p,
+                         (const unsigned long long*)cursor.p, gcap, offsets.p, counts.p, list.p);
       hipLaunchKernelGGL(exact_sum_kernel, dim3(grid_of(nt, kSumWaves)), dim3(64 * kSumWaves), 0, s, offsets.p,
                          list.p, acc.p, nt);
       TCT_HIP(hipGetLastError());

@@ -27,13 +27,18 @@ struct alignas(16) GatherRecord {
   int32_t tet;
   int32_t scale;
 };
-// The fill walk's output: counts[tet] counts the tetrahedron's records;
-// cursor counts all records, also those beyond cap, which are not written.
+// The fill walk's output: counts[tet] counts the tetrahedron's records.
+// Each workgroup writes its records into one of kGatherGroups regions of
+// rec (gcap records each; the region a hash of the block index),
+// positions handed out by that region's cursor, so no single counter
+// serialises the whole launch; cursor[g] counts all of the
+// region's records, also those beyond gcap, which are not written.
+constexpr int kGatherGroups = 64;
 struct GatherOut {
   GatherRecord* rec;
   int32_t* counts;
-  unsigned long long* cursor;
-  int64_t cap;
+  unsigned long long* cursor;  // [kGatherGroups]
+  int64_t gcap;
 };
 
 tct_status launch_pixel_walk(int mode, const tct_mesh* m, const tct_geom* g, int a0, int na_chunk,

@@ -375,8 +375,17 @@ __device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int
   return true;
 }
 
+// The record region of this workgroup: a multiplicative hash of the block
+// index, so that every region gets a fair share of the detector's central
+// (long-ray) and outer blocks whatever the tiling.
+__device__ __forceinline__ unsigned gather_group() {
+  static_assert(kGatherGroups == 64, "the region is the hash's top 6 bits");
+  return ((unsigned)blockIdx.x * 2654435761u) >> 26;
+}
+
+// Record number p of this workgroup's region.
 __device__ __forceinline__ void gather_record(const GatherOut& g, int64_t p, int tet, int scale, long long m) {
-  if (p < g.cap) g.rec[p] = GatherRecord{m, tet, scale};
+  if (p < g.gcap) g.rec[(int64_t)gather_group() * g.gcap + p] = GatherRecord{m, tet, scale};
   // Counted here, where the atomic's latency hides behind the walk (a
   // separate pass over the records took three times as long).
   atomicAdd(g.counts + tet, 1);
@@ -534,7 +543,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
         if constexpr (MODE == kModeBackFixed) {
           atomicAdd(o.acc64 + tet, (unsigned long long)m);
         } else if constexpr (MODE == kModeGatherFill) {
-          const int64_t p = (int64_t)atomicAdd(o.gather.cursor, 1ull);
+          const int64_t p = (int64_t)atomicAdd(o.gather.cursor + gather_group(), 1ull);
           gather_record(o.gather, p, tet, o.scale_exp, m);
         } else {
           unsafeAtomicAdd(o.xhat + tet, ldexpf(v, -o.scale_exp));
@@ -771,7 +780,8 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
         unsigned total = 0;
         for (int k = lane; k < kSlots; k += 64) total += __popcll(__ballot(keys[k] >= 0 && vals[k] != 0));
         unsigned long long base = 0;
-        if (lane == 0 && total) base = atomicAdd(o.gather.cursor, (unsigned long long)total);
+        if (lane == 0 && total)
+          base = atomicAdd(o.gather.cursor + gather_group(), (unsigned long long)total);
         base = ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
                (unsigned)__builtin_amdgcn_readfirstlane((int)base);
         for (int k = lane; k < kSlots; k += 64) {
