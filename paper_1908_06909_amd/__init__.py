@@ -14,7 +14,8 @@ from .solvers import CGLS, OSSART, TetProject, cgls, os_sart, project, sirt  # n
 
 __all__ += ["TetProject", "project", "CGLS", "cgls", "sirt", "OSSART", "os_sart"]
 
-from .batch import BatchCGLS, BatchProjector, PlainCGLS, SetOps, VecSet  # noqa: E402
+from .batch import BatchCGLS, BatchProjector, BatchTetProject, PlainCGLS, SetOps, VecSet, project_batch  # noqa: E402
 from . import autotune  # noqa: E402
 
-__all__ += ["VecSet", "SetOps", "BatchProjector", "BatchCGLS", "PlainCGLS", "autotune"]
+__all__ += ["VecSet", "SetOps", "BatchProjector", "BatchTetProject", "project_batch", "BatchCGLS", "PlainCGLS",
+            "autotune"]

@@ -111,6 +111,40 @@ class BatchProjector:
             self._h = None
 
 
+class BatchTetProject(torch.autograd.Function):
+    """(b_0, ..., b_{n-1}) = (A_0 x_0, ..., A_{n-1} x_{n-1}) for every problem of
+    a BatchProjector in one launch, with dL/dx_k = A_k^T dL/db_k for all k in
+    one batched backprojection launch (the batched form of TetProject)."""
+
+    @staticmethod
+    def forward(ctx, batch: "BatchProjector", *xs: torch.Tensor):
+        ctx.batch = batch
+        dev = batch.device
+        xs = [x.detach().contiguous() for x in xs]
+        outs = [torch.empty(P.geom.shape, dtype=torch.float32, device=dev) for P in batch.projectors]
+        batch.forward(VecSet(xs), VecSet(outs))
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *grads: torch.Tensor):
+        batch = ctx.batch
+        dev = batch.device
+        gs = [torch.zeros(P.geom.shape, dtype=torch.float32, device=dev) if g is None
+              else g.detach().contiguous().to(torch.float32) for g, P in zip(grads, batch.projectors)]
+        xh = [torch.empty(P.nt, dtype=torch.float32, device=dev) for P in batch.projectors]
+        batch.backproject(VecSet(gs), VecSet(xh))
+        return (None, *xh)
+
+
+def project_batch(batch: "BatchProjector", xs: Sequence[torch.Tensor]) -> List[torch.Tensor]:
+    """Differentiable forward projections of every problem of `batch` (x_k
+    float32 [nt_k], internal order; each result shaped like the problem's
+    projections, as `project` returns them), one launch per direction."""
+    if len(xs) != batch.n:
+        raise ValueError(f"expected {batch.n} tensors, got {len(xs)}")
+    return list(BatchTetProject.apply(batch, *xs))
+
+
 class BatchCGLS:
     """CGLS on every problem of a batch at once; one iteration is nine launches.
 

@@ -1096,7 +1096,16 @@ __global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __r
     const long long block = (long long)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(raw >> 32))
                                          << 32) |
                                         (unsigned)__builtin_amdgcn_readfirstlane((int)raw));
-    const BatchDesc d = D[p];
+    // A reference into the constant address space: the descriptor's fields
+    // are invariant, so the compiler may reload them with scalar loads
+    // instead of spilling them around the walk (which it did with a copy).
+    // (The host pass, which only checks the kernel, has no such space.)
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef __attribute__((address_space(4))) const BatchDesc cdesc;
+#else
+    typedef const BatchDesc cdesc;
+#endif
+    cdesc& d = ((cdesc*)D)[p];
     BlockIO io{};
     io.entry = d.entry;
     io.in = ins[d.user];

@@ -194,3 +194,49 @@ def test_batch_autotune_tiles_and_queue_chunk_then_same_results():
         B.set_queue_chunk(0)
     for P in Ps:
         assert P.mesh.stats(reset=True)["failed"] == 0
+
+
+def test_batched_autograd_matches_per_problem_autograd():
+    """The batched autograd Function (one launch per direction for all
+    problems): projections equal the per-problem TetProject ones bit for
+    bit, the gradients of sum_k 0.5 |A_k x_k - b_k|^2 match the per-problem
+    gradients (the two backprojections add the same terms in different
+    float orders), and steepest-descent steps with exact line search driven
+    by those gradients follow the same losses."""
+    tct = _tct()
+    probs = problems()
+    Ps = [P for _, P in probs]
+    B = tct.BatchProjector(Ps)
+    rng = np.random.default_rng(11)
+    bs = [torch.as_tensor(rng.uniform(0, 1, P.geom.nrays).astype(f32), device=DEV).reshape(P.geom.shape)
+          for P in Ps]
+    xb = [torch.as_tensor(rng.uniform(0, 1, P.nt).astype(f32), device=DEV) for P in Ps]
+    xp = [x.clone() for x in xb]
+    losses_b, losses_p = [], []
+    for it in range(3):
+        vb = [x.clone().requires_grad_() for x in xb]
+        vp = [x.clone().requires_grad_() for x in xp]
+        pb = tct.project_batch(B, vb)
+        pp = [tct.project(v, P) for v, P in zip(vp, Ps)]
+        if it == 0:
+            for a, c in zip(pb, pp):
+                assert torch.equal(a.detach(), c.detach())
+        lb = [0.5 * ((p - b) ** 2).sum() for p, b in zip(pb, bs)]
+        lp = [0.5 * ((p - b) ** 2).sum() for p, b in zip(pp, bs)]
+        sum(lb).backward()
+        sum(lp).backward()
+        for v1, v2 in zip(vb, vp):
+            scale = float(v2.grad.abs().max())
+            assert torch.allclose(v1.grad, v2.grad, rtol=1e-5, atol=1e-6 * scale), it
+        losses_b.append([float(l.detach()) for l in lb])
+        losses_p.append([float(l.detach()) for l in lp])
+        # x <- x - alpha g with alpha = |g|^2 / |A g|^2 (exact for least squares)
+        gb = [v.grad.detach() for v in vb]
+        gp = [v.grad.detach() for v in vp]
+        agb = tct.project_batch(B, gb)
+        agp = [P.forward(g) for g, P in zip(gp, Ps)]
+        xb = [x - (g.square().sum() / a.square().sum()) * g for x, g, a in zip(xb, gb, agb)]
+        xp = [x - (g.square().sum() / a.square().sum()) * g for x, g, a in zip(xp, gp, agp)]
+    lb, lp = np.array(losses_b), np.array(losses_p)
+    assert np.all(lb[1:] < lb[:-1])
+    assert np.allclose(lb, lp, rtol=1e-4, atol=0), (lb, lp)
