@@ -308,7 +308,7 @@ __device__ int find_entry(const MeshView& M, const Ray& r, St& st) {
 // of the terms that matter.  Terms below 2^51 in magnitude are converted to
 // integers with one float64 addition (round_to_i64).
 constexpr int kScatterSlots = 384;
-constexpr int kScatterWindow = 32;
+constexpr int kScatterWindow = 28;
 constexpr int kListSlots = 768;
 constexpr int kListWindow = 64;
 constexpr int kLdsProbes = 8;
