@@ -239,7 +239,7 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
 #define TCT_BP_ATOMIC 0        /* ray-driven float32 scatter (Section II-F); each wavefront (an 8x8-pixel tile)
                                   first sums its segments per tetrahedron in on-chip memory over windows of
                                   steps (64-bit fixed point scaled to the wavefront's largest |y_j| |P_j - S|:
-                                  every term is kept to 2^-54 of it), then adds one float atomic per distinct
+                                  every term is kept to 2^-51 of it), then adds one float atomic per distinct
                                   tetrahedron to xhat */
 #define TCT_BP_GATHER 1        /* deterministic: explicit per-tetrahedron lists of the wavefronts' exact
                                   fixed-point partial sums (one per wavefront and window of steps that crosses
@@ -247,11 +247,11 @@ tct_status tct_forward(const tct_mesh* m, const tct_geom* g, const float* x, flo
                                   not depend on the order of the list */
 #define TCT_BP_ATOMIC_DIRECT 2 /* one float32 atomic add to xhat per segment, as in the paper */
 #define TCT_BP_FIXED 4         /* reproducible ray-driven scatter: the atomic walk with every term rounded to
-                                  a multiple of 2^-s, one s per launch (terms stay below 2^(62 - ceil(log2
-                                  rays)) in magnitude), so all sums are exact integers and the result is the
-                                  same bits on every run; terms far below the launch's largest |y_j| |P_j - S|
-                                  lose relative precision (quantum 2^-(62 - ceil(log2 rays)) times the
-                                  power of two above it) */
+                                  a multiple of 2^-s, one s per launch (terms stay below 2^K in magnitude,
+                                  K = min(50, 62 - ceil(log2 rays))), so all sums are exact integers and the
+                                  result is the same bits on every run; terms far below the launch's largest
+                                  |y_j| |P_j - S| lose relative precision (quantum 2^-K times the power of
+                                  two above it) */
 #define TCT_BP_SHADOW 3        /* deterministic, element-driven: each tetrahedron enumerates the pixels of
                                   its detector shadow per angle, keeps the rays that cross it (the walk's
                                   exact predicate) and sums length x y_j in float64 in a fixed order
