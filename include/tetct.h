@@ -413,8 +413,11 @@ tct_status tct_vecset_fill(const tct_vecset* y, float value, tct_stream s);
  * caches from tct_entry / tct_entry_raster; for NULL (or NULL elements) the
  * batch computes its own caches by boundary projection (device memory it
  * frees in tct_batch_destroy; synchronises the device).  The
- * handles must outlive the batch.  A batch is stream-exclusive: its work
- * counter is reset by each call. */
+ * handles must outlive the batch.  The launches take pixel blocks from eight
+ * device work lists, one per die of the chip, each holding one contiguous
+ * run of every problem's blocks (most expensive problem first); a workgroup
+ * takes from its own die's list, then from the others'.  A batch is
+ * stream-exclusive: its list counters are reset by each call. */
 tct_status tct_batch_create(const tct_mesh* const* meshes, const tct_geom* const* geoms, int32_t n,
                             const int32_t* tile_u, int32_t* const* entries, tct_batch** out);
 /* proj_k = A_k x_k for every problem (x: nt_k floats, internal order; proj: rays_k floats). */
@@ -422,10 +425,10 @@ tct_status tct_batch_forward(tct_batch* b, const tct_vecset* x, const tct_vecset
 /* xhat_k (+)= A_k^T proj_k for every problem (atomic mode with on-chip pre-summing). */
 tct_status tct_batch_backproject(tct_batch* b, const tct_vecset* proj, const tct_vecset* xhat, int accumulate,
                                  tct_stream s);
-/* Total pixel blocks (queue items) of the batch. */
+/* Total pixel blocks (work-list items) of the batch. */
 int64_t tct_batch_items(const tct_batch* b);
-/* Pixel blocks a workgroup of the persistent batched launch takes from the
- * work queue per fetch (1..64, default 1; else TCT_E_ARG).  The pixel block
+/* Pixel blocks a workgroup of the persistent batched launch takes from a
+ * work list per fetch (1..64, default 1; else TCT_E_ARG).  The pixel block
  * shape follows the paper's thread-block tuning (Section II-F); the queue
  * granularity is the batched launch's second tuned knob.  Applies to later
  * tct_batch_forward / tct_batch_backproject calls. */

@@ -10,7 +10,7 @@ tuned here, both on the persistent batched kernel itself:
   backprojection), at least `min_rays` rays of them so that launch overhead
   does not decide;
 * for the whole batch, the number of pixel blocks a workgroup takes from the
-  work queue per fetch: each candidate is timed on the batch of all problems
+  work lists per fetch: each candidate is timed on the batch of all problems
   restricted to the same angles, with the tiles just chosen.
 
 Each candidate is run `reps` times after a warm-up and scored by its fastest

@@ -1,7 +1,8 @@
 """Batched projection and reconstruction over many independent problems.
 
 One persistent launch walks the pixel blocks of every problem (each with its
-own mesh and cone-beam geometry) from a device work queue; vector arguments
+own mesh and cone-beam geometry) from device work lists (one per die of the
+chip, each a contiguous run of every problem's blocks); vector arguments
 are device-resident pointer tables ("vector sets"), so one CGLS iteration over
 all problems is a fixed sequence of library launches with no host data and
 can be captured once and replayed as a HIP graph.
@@ -94,7 +95,7 @@ class BatchProjector:
         self.queue_chunk = 1
 
     def set_queue_chunk(self, blocks_per_fetch: int):
-        """Pixel blocks a workgroup takes from the work queue per fetch (1..64)."""
+        """Pixel blocks a workgroup takes from a work list per fetch (1..64)."""
         call("tct_batch_set_queue_chunk", self._h, int(blocks_per_fetch))
         self.queue_chunk = int(blocks_per_fetch)
 
