@@ -255,7 +255,7 @@ tct_status backproject_gather(const tct_mesh* m, const tct_geom* g, const float*
     int na_c = (int)std::max<double>(1.0, std::min<double>(a_end - a0, std::floor(kBudget / rec_per_angle)));
     // Per region: an even share of the expected records, with room for the
     // regions' spread.
-    int64_t gcap = std::max<int64_t>(1024, (int64_t)(rec_per_angle * na_c * 1.25) / kGatherGroups);
+    int64_t gcap = std::max<int64_t>(256, (int64_t)(rec_per_angle * na_c * 1.25) / kGatherGroups);
     int64_t total = 0, most = 0;
     unsigned long long need[kGatherGroups];
     for (;;) {
