@@ -261,8 +261,13 @@ __global__ __launch_bounds__(kShadowThreads, 4) void shadow_fast_kernel(ShadowAr
   const float* vt = A.G.vt;
   const int nt = A.M.nt;
   const int lane = threadIdx.x;
-  const int t = blockIdx.x * kShadowThreads + lane;
-  const int chunk = blockIdx.y;
+  // XCD-aware order (xcd_block): each die takes one contiguous run of
+  // tetrahedra (neighbours in the mesh order), whose shadows cover one region
+  // of the detector, so its L2 holds that region's projection values.
+  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
+  const int64_t blk = xcd_block((int64_t)blockIdx.y * gridDim.x + blockIdx.x, nblk);
+  const int t = (int)(blk % gridDim.x) * kShadowThreads + lane;
+  const int chunk = (int)(blk / gridDim.x);
   const int a_begin = A.a0 + chunk * A.chunk_len;
   const int a_end = min(A.a0 + A.na, a_begin + A.chunk_len);
   ShadowStats st;
