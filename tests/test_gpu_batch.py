@@ -10,6 +10,7 @@ import torch
 
 import oracle
 import synth
+from parity_bars import assert_within, backprojection_reference, element_size
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -67,12 +68,15 @@ def test_batch_backprojection_matches_plain_and_oracle():
     B = tct.BatchProjector(Ps)
     outs = [torch.full((P.nt,), 3.0, device=DEV) for P in Ps]
     B.backproject(tct.VecSet(ys), tct.VecSet(outs))
-    for (w, P), y, o in zip(probs, ys, outs):
+    for k, ((w, P), y, o) in enumerate(zip(probs, ys, outs)):
         ref_plain = P.backproject(y)
         assert torch.allclose(o, ref_plain, rtol=1e-5, atol=1e-6)
+        # Every element against the oracle at the float-atomic scatter's bar.
         orc = oracle.Oracle(w.verts, w.tets, w.cone, w.angles)
-        ref = orc.backproject(y.cpu().numpy())
+        H = element_size(w.verts, w.tets, orc.mesh.tables()[1])
+        ref, tol = backprojection_reference(orc, y.cpu().numpy(), H, float_atomic=True)
         got = P.mesh.to_user(o).cpu().numpy()
+        assert_within(got, ref, tol, f"batched backprojection, problem {k}")
         assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
 
 
