@@ -8,11 +8,15 @@ projected onto the detector and tested exactly, cached for the step) +
 forward projection A x + atomic backprojection A^T b of that projection.  The value is tet-segments (walk steps, zero-length
 passages included) per second over both walks.
 
-Prints one JSON line.  Options: --steps K (timed, default 5; kernel times
-are medians over the steps), --warmup W (default 2), --gpus N (1 only),
---no-cpu-baseline, --gather (also time the deterministic gather
-backprojection), --json-extra FILE (write per-kernel details),
---cgls-problems N (default 32; 0 skips the batched-vs-plain CGLS leg).
+Prints one JSON line.  Main options: --steps K (timed, default 5; kernel
+times are medians over the steps), --warmup W (default 2), --gpus N (1
+only), --bp MODE (backprojection of the step: atomic, fixed, shadow,
+atomic_direct or gather), --gather (also time the gather backprojection as
+a variant), --angles N (first N angles only, for profiling passes),
+--no-cpu-baseline, --json-extra FILE (per-kernel details), --cgls-problems N
+(default 32; 0 skips the batched-vs-plain CGLS leg).  Other modes replace
+the line: --batch-cgls N, --os-sart BLOCK, --paper-mode, --init-sweep
+SIZES, --copy-calibration BYTES (see --help).
 The line's `batched_cgls` object is the metric's second half: CGLS
 iterations over the 32-problem ladder in one graph-replayed persistent
 launch per direction (autotuned tiles and queue chunk) against one solver
@@ -411,8 +415,9 @@ def batch_cgls_bench(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md "
-                                   "and not launched", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this projector runs on one GPU only: sharding over several GPUs "
+                                   "(by angle, one all-reduce for the backprojection) is not launched",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
