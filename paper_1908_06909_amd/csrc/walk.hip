@@ -363,13 +363,19 @@ __device__ __forceinline__ bool lds_accumulate(lds_i32* keys, lds_i64* vals, int
                                                int claimed) {
   int k = claimed;
   if (k != -1 && k != tet) {
+    // The first probe is written out: it settles nearly every displaced key,
+    // and the loop's bookkeeping then only runs when it fails.
+    slot = slot + 1 == (unsigned)kSlots ? 0u : slot + 1;
+    k = lds_cas(keys + slot, tet);
+    if (k != -1 && k != tet) {
 #pragma unroll 1
-    for (int p = 1; p < kLdsProbes; ++p) {
-      slot = slot + 1 == (unsigned)kSlots ? 0u : slot + 1;
-      k = lds_cas(keys + slot, tet);
-      if (k == -1 || k == tet) break;
+      for (int p = 2; p < kLdsProbes; ++p) {
+        slot = slot + 1 == (unsigned)kSlots ? 0u : slot + 1;
+        k = lds_cas(keys + slot, tet);
+        if (k == -1 || k == tet) break;
+      }
+      if (k != -1 && k != tet) return false;
     }
-    if (k != -1 && k != tet) return false;
   }
   __hip_atomic_fetch_add(vals + slot, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   return true;
@@ -471,11 +477,13 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, cons
 
 // One step: leave the current tetrahedron, apply the mode's action for its
 // segment, move to the neighbour.  Returns false once the ray has left the
-// mesh (or the walk failed).
-template <int MODE, class Src, class St>
+// mesh (or the walk failed).  kLimit: the step bounds the walk itself (a ray
+// never crosses more than nt elements); the windowed walks bound it once per
+// window instead.
+template <int MODE, bool kLimit = true, class Src, class St>
 __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const Src& q, WalkState& w,
                                           WalkOut<MODE>& o, St& st) {
-  if (w.steps > M.nt) {
+  if (kLimit && w.steps > M.nt) {
     st.add_failed();
     st.steps += w.steps;
     return false;
@@ -535,19 +543,20 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   if constexpr (MODE == kModeForward) {
     o.acc = fma((double)dt, (double)w.xcur, o.acc);  // the product is exact
   } else if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
-    if (dt > 0.f) {
-      const float v = dt * o.weight;  // in units of 2^-scale_exp
-      const long long m = round_to_i64(v);
-      if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m,
-                                                   table_home<TableShape<MODE>::slots>(tet), w.claim)) {
-        if constexpr (MODE == kModeBackFixed) {
-          atomicAdd(o.acc64 + tet, (unsigned long long)m);
-        } else if constexpr (MODE == kModeGatherFill) {
-          const int64_t p = (int64_t)atomicAdd(o.gather.cursor + gather_group(), 1ull);
-          gather_record(o.gather, p, tet, o.scale_exp, m);
-        } else {
-          unsafeAtomicAdd(o.xhat + tet, ldexpf(v, -o.scale_exp));
-        }
+    // Every segment goes into the table, a zero-length one as 0 (dt is never
+    // negative or NaN after the clamp): adding zero costs less than a branch
+    // per step, and the step's claim is then consumed on every path.
+    const float v = dt * o.weight;  // in units of 2^-scale_exp
+    const long long m = round_to_i64(v);
+    if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m,
+                                                 table_home<TableShape<MODE>::slots>(tet), w.claim)) {
+      if constexpr (MODE == kModeBackFixed) {
+        atomicAdd(o.acc64 + tet, (unsigned long long)m);
+      } else if constexpr (MODE == kModeGatherFill) {
+        const int64_t p = (int64_t)atomicAdd(o.gather.cursor + gather_group(), 1ull);
+        gather_record(o.gather, p, tet, o.scale_exp, m);
+      } else {
+        unsafeAtomicAdd(o.xhat + tet, ldexpf(v, -o.scale_exp));
       }
     }
   } else if constexpr (MODE == kModeBackDirect) {
@@ -760,6 +769,10 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       o.lds_scale = ldexpf(1.0f, o.scale_exp);
     }
     o.weight *= o.lds_scale;  // a power of two: exact
+    // The wavefront's rays start together and every live one takes one step
+    // per iteration, so all of them have taken `taken` steps at a window's
+    // start: the step bound is checked there, once per window.
+    int taken = 0;
     // The wavefront's rays advance together in windows of kWindow
     // steps; after each window its table is added to xhat and cleared, so it
     // only ever holds the tetrahedra of one window of the ray bundle.
@@ -767,8 +780,14 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
       // Each step claims the slot of the tetrahedron it enters (walk_step);
       // the flush has cleared the table, so the current ones claim again.
       if (alive) w.claim = lds_cas(keys + table_home<kSlots>(w.tet), w.tet);
+      if (taken > M.nt && alive) {
+        st.add_failed();
+        st.steps += w.steps;
+        alive = false;
+      }
 #pragma unroll 1
-      for (int k = 0; k < kWindow && alive; ++k) alive = walk_step<MODE>(M, r, q, w, o, st);
+      for (int k = 0; k < kWindow && alive; ++k) alive = walk_step<MODE, false>(M, r, q, w, o, st);
+      taken += kWindow;
       // LDS operations of one wavefront complete in order: the flush sees
       // every add of the window.
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");

