@@ -505,7 +505,7 @@ def main():
     bwd_gbs = BWD_BYTES_PER_SEG * segs_per_walk / (ms["backproject"] * 1e-3) / 1e9
     bp_kernel = {"atomic": "atomic backprojection walk (pixel_walk_kernel<2>)",
                  "atomic_direct": "direct-atomic backprojection walk (pixel_walk_kernel<7>)",
-                 "gather": "gather backprojection (walk fill + sort + segment sum)",
+                 "gather": "gather backprojection (walk fill + records into lists + exact sums)",
                  "fixed": "reproducible fixed-point scatter (pixel_walk_kernel<9>)",
                  "shadow": "element-driven backprojection (shadow_fast_kernel + shadow_exact_kernel)"}[args.bp]
     if ms["forward"] >= ms["backproject"]:
