@@ -107,6 +107,30 @@ __host__ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n) {
 #endif
 }
 
+// Local-index remap, tabulated for the walk.  The walk keeps the local indices of its
+// three entry-face slots and of v in 2-bit fields of one byte (slot j in bits
+// 2j, v in bits 6-7).  Leaving through the face opposite slot k into a
+// neighbour whose opposite vertex has local index `back`, every index p
+// becomes r + (r >= back) with r = p - (p > f), f = the index in slot k; slot
+// k then takes v's new index and v's field takes `back`.  The entry for
+// (byte, k, back) sits at (byte * 3 + k) * 4 + back; bytes that are not
+// permutations map to values the walk never reads.
+constexpr int kLocRemapEntries = 256 * 3 * 4;
+
+constexpr unsigned loc_remap_entry(unsigned i) {
+  const unsigned L = i / 12u, k = (i / 4u) % 3u, back = i % 4u;
+  const unsigned f = (L >> (2u * k)) & 3u;
+  unsigned out = 0;
+  for (unsigned s = 0; s < 4; ++s) {
+    const unsigned p = (L >> (2u * s)) & 3u;
+    const unsigned r = p - (p > f ? 1u : 0u);
+    out |= ((r + (r >= back ? 1u : 0u)) & 3u) << (2u * s);
+  }
+  const unsigned vnew = (out >> 6) & 3u;
+  out = (out & ~(3u << (2u * k))) | (vnew << (2u * k));
+  return (out & 0x3Fu) | (back << 6);
+}
+
 void set_error(const std::string& msg);
 tct_status hip_fail(hipError_t e, const char* what);
 

@@ -425,7 +425,9 @@ struct WalkOut {
 // Walk state between steps: the entry face as three vertex slots, the
 // fourth vertex v, the current tetrahedron and the ray parameter where the
 // ray entered it.  `loc` holds the local indices (0..3 within the current
-// tetrahedron) of slots 0, 1, 2 and of v in four 4-bit fields.
+// tetrahedron) of slots 0, 1, 2 and of v: in four 2-bit fields of one byte
+// for the walks that remap it through the LDS table (loc_table), in four
+// 4-bit fields for the bit-parallel remap of the others.
 //
 // Crossing face f (the face opposite local vertex f) into a neighbour whose
 // opposite vertex has local index `back` there, the three shared vertices
@@ -447,6 +449,37 @@ struct WalkState {
   bool far;
 };
 
+// Local-index remap as a table of loc_remap_entry (common.h), one byte per
+// (loc, k, back), copied into each block's LDS by the walks that use it.
+struct alignas(4) LocRemap {
+  unsigned char v[kLocRemapEntries];
+};
+
+constexpr LocRemap make_loc_remap() {
+  LocRemap t{};
+  for (unsigned i = 0; i < (unsigned)kLocRemapEntries; ++i) t.v[i] = (unsigned char)loc_remap_entry(i);
+  return t;
+}
+
+__constant__ LocRemap kLocRemap = make_loc_remap();
+
+// The walks that look the remap up in LDS (a read per step in place of about
+// fifteen vector instructions); the others keep the bit-parallel remap.
+constexpr bool loc_table(int MODE) {
+  return MODE == kModeForward || MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill;
+}
+
+__shared__ __align__(4) unsigned char s_loc_remap[kLocRemapEntries];
+
+// Copies the remap table into the block's LDS; every thread of the block
+// calls it before its first step.
+__device__ __forceinline__ void load_loc_remap() {
+  const unsigned* src = reinterpret_cast<const unsigned*>(kLocRemap.v);
+  unsigned* dst = reinterpret_cast<unsigned*>(s_loc_remap);
+  for (int i = threadIdx.x; i < kLocRemapEntries / 4; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+}
+
 // Enter the mesh through boundary face `entry`.
 template <int MODE, class Src>
 __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, const Src& q, int entry, WalkState& w,
@@ -456,7 +489,10 @@ __device__ __forceinline__ void walk_start(const MeshView& M, const Ray& r, cons
   float4 q0 = bq[0], q1 = bq[1], q2 = bq[2], q3 = bq[3];
   w.tet = __float_as_int(q0.w);
   unsigned lp = (unsigned)__float_as_int(q1.w);
-  w.loc = (lp & 3u) | ((lp & 12u) << 2) | ((lp & 48u) << 4) | ((lp & 192u) << 6);
+  if constexpr (loc_table(MODE))
+    w.loc = lp & 0xFFu;
+  else
+    w.loc = (lp & 3u) | ((lp & 12u) << 2) | ((lp & 48u) << 4) | ((lp & 192u) << 6);
   w.a0 = make_float3(q0.x, q0.y, q0.z);
   w.a1 = make_float3(q1.x, q1.y, q1.z);
   w.a2 = make_float3(q2.x, q2.y, q2.z);
@@ -514,7 +550,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   // record's load is issued as soon as the face is known, so that its
   // latency overlaps the crossing and the segment's accumulation.
   const int tet = w.tet;
-  const unsigned sh = 4u * (unsigned)k;
+  const unsigned sh = (loc_table(MODE) ? 2u : 4u) * (unsigned)k;
   unsigned f = (w.loc >> sh) & 3u;
   float4 rec = M.faces[(size_t)(((unsigned)tet << 2) | f)];
   const bool k0 = k == 0, k2 = k == 2;
@@ -570,13 +606,14 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   }
   // What does not need the record is done while it is in flight: the entry
   // slots (slot k takes v), the ray parameter, and the first half of the
-  // local-index remap.  All four index fields at once: adding 7 - f to a
-  // field sets its bit 3 exactly when p > f, and adding 8 - back to the rank
-  // sets it exactly when r >= back; the fields hold at most 10, so no carry
-  // crosses into the next.  (The field of slot k, whose vertex is not on the
-  // face, is replaced.)
+  // local-index remap: the table row (loc, k), or, bit-parallel, all four
+  // index fields at once: adding 7 - f to a field sets its bit 3 exactly
+  // when p > f, and adding 8 - back to the rank sets it exactly when r >=
+  // back; the fields hold at most 10, so no carry crosses into the next.
+  // (The field of slot k, whose vertex is not on the face, is replaced.)
   const unsigned L = w.loc;
-  const unsigned R = L - (((L + 0x7777u - f * 0x1111u) >> 3) & 0x1111u);
+  const unsigned R = loc_table(MODE) ? (L * 3u + (unsigned)k) * 4u
+                                     : L - (((L + 0x7777u - f * 0x1111u) >> 3) & 0x1111u);
   w.a0 = make_float3(k == 0 ? v.x : w.a0.x, k == 0 ? v.y : w.a0.y, k == 0 ? v.z : w.a0.z);
   w.a1 = make_float3(k == 1 ? v.x : w.a1.x, k == 1 ? v.y : w.a1.y, k == 1 ? v.z : w.a1.z);
   w.a2 = make_float3(k == 2 ? v.x : w.a2.x, k == 2 ? v.y : w.a2.y, k == 2 ? v.z : w.a2.z);
@@ -596,10 +633,15 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     return false;
   }
   unsigned back = (unsigned)packed & 3u;
-  const unsigned N = Rk + (((Rk + 0x8888u - back * 0x1111u) >> 3) & 0x1111u);
-  // Slot k takes v's new index; the neighbour's opposite vertex is `back`.
-  const unsigned fieldk = 0xFu << sh;
-  w.loc = (((N & 0xFFFu) & ~fieldk) | ((N >> 12) << sh)) | (back << 12);
+  if constexpr (loc_table(MODE)) {
+    // Read back while the next step computes; needed at its exit face.
+    w.loc = s_loc_remap[Rk + back];
+  } else {
+    const unsigned N = Rk + (((Rk + 0x8888u - back * 0x1111u) >> 3) & 0x1111u);
+    // Slot k takes v's new index; the neighbour's opposite vertex is `back`.
+    const unsigned fieldk = 0xFu << sh;
+    w.loc = (((N & 0xFFFu) & ~fieldk) | ((N >> 12) << sh)) | (back << 12);
+  }
   w.v = xyz(rec);
   w.tet = packed >> 2;
   // Table walks claim the new tetrahedron's home slot now; the old key comes
@@ -880,6 +922,7 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
 template <int MODE, bool kCached>
 __global__ __launch_bounds__(256, 4) void pixel_walk_kernel(MeshView M, GeomView G, TileMap tm, int a0, int na_chunk,
                                                          BlockIO io) {
+  if constexpr (loc_table(MODE)) load_loc_remap();
   if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
     __shared__ int tkeys[kBlockWaves * TableShape<MODE>::slots];
     __shared__ long long tvals[kBlockWaves * TableShape<MODE>::slots];
@@ -1057,6 +1100,7 @@ __global__ __launch_bounds__(256, 4) void batch_walk_kernel(const BatchDesc* __r
   // Thread 0 fetches `chunk` positions at a time and resolves each to a
   // (problem, pixel block) for the whole block; its state lives in LDS so
   // that nothing of the queue stays live in registers during the walk.
+  if constexpr (loc_table(MODE)) load_loc_remap();
   __shared__ long long s_k, s_end, s_block;
   __shared__ int s_list, s_prob;
   const int home = (int)(blockIdx.x % kXcds);

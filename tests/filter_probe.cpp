@@ -76,3 +76,6 @@ int probe_exit_table(int n_neg_bits) {
 
 // XCD-aware block order (common.h) for one launch of n blocks.
 extern "C" long long probe_xcd_block(long long b, long long n) { return (long long)xcd_block(b, n); }
+
+// Entry i of the walk's local-index remap table (common.h).
+extern "C" unsigned probe_loc_remap(unsigned i) { return loc_remap_entry(i); }

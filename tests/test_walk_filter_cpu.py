@@ -67,6 +67,8 @@ def _build_probe(tag, extra):
     L.probe_exit_table.argtypes = [C.c_int]
     L.probe_xcd_block.argtypes = [C.c_longlong, C.c_longlong]
     L.probe_xcd_block.restype = C.c_longlong
+    L.probe_loc_remap.argtypes = [C.c_uint]
+    L.probe_loc_remap.restype = C.c_uint
     return L
 
 
@@ -352,3 +354,38 @@ def test_xcd_block_order_is_a_bijection_with_one_run_per_die(probe, n):
         run = L[x::8]
         if len(run):
             assert np.array_equal(run, np.arange(run[0], run[0] + len(run)))
+
+
+def test_local_index_remap_table_follows_sorted_ranks(probe):
+    """The library numbers an element's vertices by ascending node id (mesh
+    ingest), so a vertex's local index is its rank among the element's four
+    node ids, and face neighbours share three of them (Section II-B, Fig. 1).
+    Every entry of the remap table the walks read, for every slot order, exit
+    slot k and rank of the new vertex, must give the ranks of the slots in the
+    neighbour across the face opposite slot k: slot k takes the old v, v the
+    neighbour's new vertex."""
+    rng = np.random.default_rng(5)
+    import itertools
+
+    n = 0
+    for perm in itertools.permutations(range(4)):
+        for k in range(3):
+            for back in range(4):
+                # Four ids of the current element, sorted; slot s holds rank perm[s].
+                ids = np.sort(rng.choice(1000, 4, replace=False)) * 4 + 4
+                slots = [int(ids[p]) for p in perm]  # a0, a1, a2, v
+                gone = slots[k]
+                shared = sorted(x for x in ids.tolist() if x != gone)
+                # A new vertex whose rank among the neighbour's ids is `back`.
+                lo = shared[back - 1] if back > 0 else 0
+                hi = shared[back] if back < 3 else 10 ** 6
+                w = (lo + hi) // 2
+                assert lo < w < hi
+                nb = sorted(shared + [w])
+                new_slots = slots[:3] + [w]
+                new_slots[k] = slots[3]
+                want = sum(nb.index(x) << (2 * s) for s, x in enumerate(new_slots))
+                loc = sum(p << (2 * s) for s, p in enumerate(perm))
+                assert probe.probe_loc_remap((loc * 3 + k) * 4 + back) == want
+                n += 1
+    assert n == 288
