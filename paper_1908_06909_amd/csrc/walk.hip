@@ -442,6 +442,7 @@ struct WalkState {
   double s_in;  // ray parameter where the ray entered the current tetrahedron
   float xcur;  // forward projection: x of the current tetrahedron
   int claim;   // table walks: old key returned by the claim of the tetrahedron's home slot
+  unsigned home;  // table walks: that home slot, kept from the claim for the step's accumulation
   int steps;
   // Every ray of the wavefront ends beyond the mesh (ends_beyond_mesh), so
   // segments need no clamp at the end point; the same for the whole
@@ -585,7 +586,7 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
     const float v = dt * o.weight;  // in units of 2^-scale_exp
     const long long m = round_to_i64(v);
     if (!lds_accumulate<TableShape<MODE>::slots>(o.lds_keys, o.lds_vals, tet, m,
-                                                 table_home<TableShape<MODE>::slots>(tet), w.claim)) {
+                                                 w.home, w.claim)) {
       if constexpr (MODE == kModeBackFixed) {
         atomicAdd(o.acc64 + tet, (unsigned long long)m);
       } else if constexpr (MODE == kModeGatherFill) {
@@ -646,8 +647,10 @@ __device__ __forceinline__ bool walk_step(const MeshView& M, const Ray& r, const
   w.tet = packed >> 2;
   // Table walks claim the new tetrahedron's home slot now; the old key comes
   // back while the next step computes, and is needed only at its end.
-  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill)
-    w.claim = lds_cas(o.lds_keys + table_home<TableShape<MODE>::slots>(w.tet), w.tet);
+  if constexpr (MODE == kModeBackAtomic || MODE == kModeBackFixed || MODE == kModeGatherFill) {
+    w.home = table_home<TableShape<MODE>::slots>(w.tet);
+    w.claim = lds_cas(o.lds_keys + w.home, w.tet);
+  }
   if constexpr (MODE == kModeForward) w.xcur = o.x[w.tet];
   return true;
 }
@@ -821,7 +824,10 @@ __device__ __forceinline__ void walk_block(const MeshView& M, const GeomView& G,
     for (;;) {
       // Each step claims the slot of the tetrahedron it enters (walk_step);
       // the flush has cleared the table, so the current ones claim again.
-      if (alive) w.claim = lds_cas(keys + table_home<kSlots>(w.tet), w.tet);
+      if (alive) {
+        w.home = table_home<kSlots>(w.tet);
+        w.claim = lds_cas(keys + w.home, w.tet);
+      }
       if (taken > M.nt && alive) {
         st.add_failed();
         st.steps += w.steps;
